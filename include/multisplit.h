@@ -1,0 +1,249 @@
+/*
+ * multisplit.h -- C ABI of the MI355X (gfx950) stable multisplit library.
+ *
+ * Paper: Ashkiani, Davidson, Meyer, Owens, "GPU Multisplit: an extended study
+ * of a parallel algorithm" (ACM TOPC 2017).
+ *
+ * Multisplit (Section 3.1): permute n keys (or key-value pairs) so that
+ * all elements of bucket 0 come first, then bucket 1, ..., then bucket m-1,
+ * where the bucket of a key is given by a bucket identifier f.  This library
+ * is always *stable*: inside a bucket the input order is kept, so the output
+ * is the unique permutation of Eq. (1) (Section 4.2):
+ *     p(i) = sum_{j < f(u_i)} h_j  +  #{ r < i : f(u_r) = f(u_i) }.
+ * It runs the paper's three stages (Section 4.6): a pre-scan that builds the
+ * bucket-major histogram matrix H (m rows, one column per subproblem), a
+ * scan of H (Eq. 2), and a post-scan that ranks every element inside its
+ * tile with wavefront ballots (Algorithms 2 and 3 on 64-lane wavefronts),
+ * reorders the tile in LDS (Section 5.6) and scatters it.
+ *
+ * Conventions for every entry point:
+ *   - Pointers named d_* are DEVICE pointers (HIP device memory or managed
+ *     memory visible to the current device).  They are owned by the caller;
+ *     the library never allocates device memory and never frees anything.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Every call only enqueues work on `stream` and returns without
+ *     synchronising; outputs are valid once the stream has completed.
+ *   - Outputs must not overlap inputs (no in-place operation).
+ *   - Arguments are validated on the host before any launch; an invalid
+ *     call enqueues nothing and leaves outputs untouched.
+ *   - Errors: see ms_status.  MS_ERR_HIP reports a failed HIP launch.
+ *   - The workspace d_ws (ws_bytes bytes, 256-byte aligned) is scratch owned
+ *     by the caller; its required size comes from ms_workspace_size().  Two
+ *     calls that run at the same time must not share a workspace.
+ *   - Indices and offsets are uint32: n must be below 2^32.
+ *   - Keys and values are 32-bit words; values are moved, never inspected.
+ */
+#ifndef MULTISPLIT_H
+#define MULTISPLIT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MS_OK = 0,
+  MS_ERR_INVALID_ARG = -1, /* bad size, null pointer, m out of [1,256], ...   */
+  MS_ERR_WORKSPACE = -2,   /* ws_bytes smaller than ms_workspace_size()      */
+  MS_ERR_HIP = -3,         /* a HIP runtime call or kernel launch failed     */
+  MS_ERR_BUCKET_RANGE = -4,/* bucket function can produce ids >= m           */
+  MS_ERR_TIMEOUT = -5,     /* a bounded device wait expired                  */
+  MS_ERR_UNSUPPORTED = -6  /* valid request this build does not implement    */
+} ms_status;
+
+/* Human-readable name of a status code (static string). */
+const char* ms_status_str(int status);
+
+/*
+ * Bucket identifiers (Section 6, "Bucket identification"; Section 7.1).
+ *   MS_BUCKET_SHIFT_MASK  f(k) = (k >> shift) & mask.  Identity buckets and
+ *                         radix digits f_p(k) = (k >> p r) & (2^r - 1) of
+ *                         Section 7.1; delta buckets of width 2^s.
+ *                         Requires mask <= m - 1.
+ *   MS_BUCKET_DIV         f(k) = floor(k / divisor): the paper's delta
+ *                         buckets of width Delta = divisor.  Requires
+ *                         (2^32 - 1) / divisor <= m - 1.
+ *   MS_BUCKET_SPLITTERS   range buckets: f(k) = number of splitters <= k,
+ *                         i.e. s_{j-1} <= k < s_j with open-ended first and
+ *                         last buckets (an upper bound over the splitters,
+ *                         Section 7.3).  `splitters` points to m-1 ascending
+ *                         uint32 in device memory (duplicates allowed: they
+ *                         make empty buckets).  Found by binary search.
+ *   MS_BUCKET_LEARNED     the same ids as MS_BUCKET_SPLITTERS, found by a
+ *                         two-stage piecewise-linear model (`model`, device
+ *                         pointer to MS_MODEL_FLOATS floats written by
+ *                         ms_learned_fit) whose prediction is then checked
+ *                         against the neighbouring splitters and corrected
+ *                         exactly (one step either way, else binary search).
+ *                         Not in the paper; the output is bit-identical to
+ *                         MS_BUCKET_SPLITTERS.
+ */
+enum {
+  MS_BUCKET_SHIFT_MASK = 0,
+  MS_BUCKET_DIV = 1,
+  MS_BUCKET_SPLITTERS = 2,
+  MS_BUCKET_LEARNED = 3
+};
+
+#define MS_MODEL_LEAVES 256
+#define MS_MODEL_FLOATS (2 + 2 * MS_MODEL_LEAVES)
+
+typedef struct {
+  int32_t kind;              /* one of MS_BUCKET_*                             */
+  uint32_t shift;            /* SHIFT_MASK                                     */
+  uint32_t mask;             /* SHIFT_MASK                                     */
+  uint32_t divisor;          /* DIV                                            */
+  const uint32_t* splitters; /* SPLITTERS, LEARNED: m-1 ascending, device      */
+  const float* model;        /* LEARNED: MS_MODEL_FLOATS floats, device        */
+} ms_bucket_fn;
+
+/*
+ * Reordering granularity (Section 5.3 and 5.6):
+ *   MS_REORDER_BLOCK  block-level multisplit (BMS): each workgroup owns a
+ *                     chunk of consecutive tiles; a tile is ranked by all of
+ *                     its wavefronts and reordered in LDS across them.
+ *   MS_REORDER_WAVE   wave-level multisplit (WMS): each wavefront owns a
+ *                     chunk and reorders its own tiles in LDS.
+ *   MS_REORDER_NONE   direct multisplit (DMS): each wavefront owns a chunk;
+ *                     elements are scattered straight from registers.
+ * All three give the same (unique) stable result.
+ */
+enum {
+  MS_REORDER_AUTO = 0,
+  MS_REORDER_BLOCK = 1,
+  MS_REORDER_WAVE = 2,
+  MS_REORDER_NONE = 3
+};
+
+/*
+ * Optional tuning and instrumentation; pass NULL for defaults.  Every field
+ * may be 0 (= choose automatically).  Tuning never changes results.
+ *   reorder          MS_REORDER_*.
+ *   waves_per_block  4 or 8 wavefronts of 64 lanes per workgroup.
+ *   items_per_lane   windows of 64 elements each wavefront ranks per tile
+ *                    (the paper's N_window): 4, 8 or 16.
+ *   max_chunks       upper bound on the number of subproblems L0 (columns
+ *                    of H); 0 = enough to fill every compute unit once.
+ *   stage_events     if non-NULL, four hipEvent_t (as void*) that are
+ *                    recorded on `stream` before the pre-scan, before the
+ *                    scan, before the post-scan and after the post-scan.
+ *   d_mispredicts    LEARNED only, optional device uint64: the number of
+ *                    keys whose raw model prediction was wrong is ADDED to
+ *                    it (the caller zeroes it).
+ */
+typedef struct {
+  int32_t reorder;
+  int32_t waves_per_block;
+  int32_t items_per_lane;
+  int32_t max_chunks;
+  void* const* stage_events;
+  uint64_t* d_mispredicts;
+} ms_options;
+
+/* Operations for ms_workspace_size(). */
+enum {
+  MS_OP_KEYS = 0,
+  MS_OP_PAIRS = 1,
+  MS_OP_BATCHED = 2,
+  MS_OP_RADIX_SORT = 3,
+  MS_OP_RADIX_SORT_PAIRS = 4,
+  MS_OP_LEARNED_FIT = 5
+};
+
+/*
+ * Bytes of workspace an operation needs.  n = elements (for MS_OP_BATCHED the
+ * total over all instances, for MS_OP_LEARNED_FIT the sample size), m =
+ * buckets, num_inst = instances (MS_OP_BATCHED only), opt as passed to the
+ * call (NULL = defaults).  Returns 0 only for arguments that are invalid.
+ */
+size_t ms_workspace_size(int op, size_t n, uint32_t m, uint32_t num_inst,
+                         const ms_options* opt);
+
+/*
+ * Stable multisplit of keys (Section 3.1, Eq. 1).
+ *   d_keys_in   n uint32 keys.
+ *   d_keys_out  n uint32: keys in ascending bucket order, input order kept
+ *               inside every bucket.
+ *   d_offsets   m+1 uint32 or NULL: d_offsets[j] = first output index of
+ *               bucket j, d_offsets[m] = n (the paper's optional bucket-start
+ *               array, Section 3.1, plus its end).
+ *   n           0 <= n < 2^32.  n = 0 writes offsets of zero.
+ *   m           1 <= m <= 256 buckets.
+ *   fn          bucket identifier (host pointer to the descriptor).
+ */
+ms_status ms_keys(const uint32_t* d_keys_in, uint32_t* d_keys_out,
+                  uint32_t* d_offsets, size_t n, uint32_t m,
+                  const ms_bucket_fn* fn, void* d_ws, size_t ws_bytes,
+                  const ms_options* opt, void* stream);
+
+/* Stable multisplit of key-value pairs: as ms_keys, and every value moves
+ * with its key (d_vals_in, d_vals_out: n uint32 each). */
+ms_status ms_pairs(const uint32_t* d_keys_in, const uint32_t* d_vals_in,
+                   uint32_t* d_keys_out, uint32_t* d_vals_out,
+                   uint32_t* d_offsets, size_t n, uint32_t m,
+                   const ms_bucket_fn* fn, void* d_ws, size_t ws_bytes,
+                   const ms_options* opt, void* stream);
+
+/*
+ * LSD radix sort built from multisplit passes (Section 7.1): with r =
+ * bits_per_pass, pass p is a stable multisplit on f_p(k) = (k >> p r) &
+ * (2^r - 1), p = 0 .. ceil(32 / r) - 1, so the result is the stable sort of
+ * the keys (values follow their keys).  d_vals_in / d_vals_out may both be
+ * NULL for a key-only sort.  bits_per_pass in [1, 8].  The workspace holds
+ * the ping-pong copy of the data.
+ */
+ms_status ms_radix_sort(const uint32_t* d_keys_in, const uint32_t* d_vals_in,
+                        uint32_t* d_keys_out, uint32_t* d_vals_out, size_t n,
+                        uint32_t bits_per_pass, void* d_ws, size_t ws_bytes,
+                        const ms_options* opt, void* stream);
+
+/*
+ * Batched stable multisplit: num_inst independent instances in one launch
+ * sequence.  Instance i is elements [d_seg[i], d_seg[i+1]) of the
+ * concatenated arrays (d_seg: num_inst+1 ascending uint64, device; d_seg[0]
+ * is normally 0; the total must be below 2^32).  Each instance is
+ * multisplit on its own into the same index range of the outputs.
+ * d_offsets: num_inst*(m+1) uint32 or NULL, instance i's bucket starts
+ * relative to its own first element (last entry = its size).  d_vals_in and
+ * d_vals_out may both be NULL.  The call does not synchronise and allocates
+ * nothing, so it can be captured into a HIP graph.
+ */
+ms_status ms_batched(const uint32_t* d_keys_in, const uint32_t* d_vals_in,
+                     uint32_t* d_keys_out, uint32_t* d_vals_out,
+                     const uint64_t* d_seg, uint32_t num_inst, size_t total,
+                     uint32_t m, const ms_bucket_fn* fn, uint32_t* d_offsets,
+                     void* d_ws, size_t ws_bytes, const ms_options* opt,
+                     void* stream);
+
+/*
+ * Fit the learned bucket model for range buckets given by m-1 ascending
+ * device splitters, from n_sample device sample keys.  Labels are the exact
+ * upper bounds.  Root: least squares of y*256/m on x = (float)key.  Every
+ * sample is routed to a leaf by the root evaluated in float; each leaf is a
+ * least-squares line of y on x; an empty leaf copies its nearest non-empty
+ * left neighbour (else right).  Sums are in double, in a fixed order, so the
+ * result is deterministic.  d_model receives MS_MODEL_FLOATS floats.
+ */
+ms_status ms_learned_fit(const uint32_t* d_sample, size_t n_sample,
+                         const uint32_t* d_splitters, uint32_t m,
+                         float* d_model, void* d_ws, size_t ws_bytes,
+                         void* stream);
+
+/*
+ * Streaming copy of n uint32 (d_dst[i] = d_src[i]).  Not part of the
+ * method: it measures the achievable HBM copy bandwidth that the multisplit
+ * kernels are compared against.
+ */
+ms_status ms_copy_u32(uint32_t* d_dst, const uint32_t* d_src, size_t n,
+                      void* stream);
+
+/* Version string of the library build. */
+const char* ms_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MULTISPLIT_H */

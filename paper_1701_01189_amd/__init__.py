@@ -1,0 +1,14 @@
+"""Stable multisplit for AMD Instinct MI355X (gfx950).
+
+Implements the three-stage multisplit of Ashkiani et al., "GPU Multisplit:
+an extended study of a parallel algorithm" (pre-scan, scan, post-scan with
+wavefront-ballot ranking and LDS reordering) as hand-written HIP kernels
+behind the C ABI in include/multisplit.h.  This package is the thin Python
+binding (``binding``), the in-tree build (``build``) and the seeded input
+generators (``inputs``).  The native library is loaded on first use.
+"""
+from .binding import (BUCKET_DIV, BUCKET_LEARNED, BUCKET_SHIFT_MASK, BUCKET_SPLITTERS,
+                      MODEL_FLOATS, OP_KEYS, OP_PAIRS, OP_RADIX_SORT, OP_RADIX_SORT_PAIRS,
+                      REORDER_AUTO, REORDER_BLOCK, REORDER_NONE, REORDER_WAVE, BucketFn,
+                      MultisplitError, Options, copy_u32, keys, pairs, radix_sort,
+                      workspace_size)

@@ -1,0 +1,248 @@
+"""Thin ctypes binding of libmultisplit.so (include/multisplit.h).
+
+Argument marshalling only: torch tensors supply device pointers, the current
+HIP stream and workspace memory; every step of the multisplit runs in the
+library's gfx950 kernels.  There is no fallback: if the library is missing
+or a call fails, an exception is raised.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmultisplit.so")
+
+MS_OK = 0
+STATUS = {0: "MS_OK", -1: "MS_ERR_INVALID_ARG", -2: "MS_ERR_WORKSPACE", -3: "MS_ERR_HIP",
+          -4: "MS_ERR_BUCKET_RANGE", -5: "MS_ERR_TIMEOUT", -6: "MS_ERR_UNSUPPORTED"}
+
+BUCKET_SHIFT_MASK, BUCKET_DIV, BUCKET_SPLITTERS, BUCKET_LEARNED = 0, 1, 2, 3
+REORDER_AUTO, REORDER_BLOCK, REORDER_WAVE, REORDER_NONE = 0, 1, 2, 3
+OP_KEYS, OP_PAIRS, OP_BATCHED, OP_RADIX_SORT, OP_RADIX_SORT_PAIRS, OP_LEARNED_FIT = range(6)
+MODEL_LEAVES = 256
+MODEL_FLOATS = 2 + 2 * MODEL_LEAVES
+
+
+class MultisplitError(RuntimeError):
+    def __init__(self, status, what):
+        super().__init__("%s failed: %s (%d)" % (what, STATUS.get(status, "?"), status))
+        self.status = status
+
+
+class BucketFnC(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("shift", ctypes.c_uint32), ("mask", ctypes.c_uint32),
+                ("divisor", ctypes.c_uint32), ("splitters", ctypes.c_void_p),
+                ("model", ctypes.c_void_p)]
+
+
+class OptionsC(ctypes.Structure):
+    _fields_ = [("reorder", ctypes.c_int32), ("waves_per_block", ctypes.c_int32),
+                ("items_per_lane", ctypes.c_int32), ("max_chunks", ctypes.c_int32),
+                ("stage_events", ctypes.c_void_p), ("d_mispredicts", ctypes.c_void_p)]
+
+
+_lib = None
+SYMBOLS = ["ms_status_str", "ms_version", "ms_workspace_size", "ms_keys", "ms_pairs",
+           "ms_radix_sort", "ms_batched", "ms_learned_fit", "ms_copy_u32"]
+
+
+def lib():
+    """Loads libmultisplit.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libmultisplit.so is not built (run __graft_entry__.build() or "
+                           "python -m paper_1701_01189_amd.build)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, sz, u32, i32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_uint32, ctypes.c_int
+    L.ms_status_str.argtypes = [i32]
+    L.ms_status_str.restype = ctypes.c_char_p
+    L.ms_version.argtypes = []
+    L.ms_version.restype = ctypes.c_char_p
+    L.ms_workspace_size.argtypes = [i32, sz, u32, u32, ctypes.POINTER(OptionsC)]
+    L.ms_workspace_size.restype = sz
+    L.ms_keys.argtypes = [vp, vp, vp, sz, u32, ctypes.POINTER(BucketFnC), vp, sz,
+                          ctypes.POINTER(OptionsC), vp]
+    L.ms_keys.restype = i32
+    L.ms_pairs.argtypes = [vp, vp, vp, vp, vp, sz, u32, ctypes.POINTER(BucketFnC), vp, sz,
+                           ctypes.POINTER(OptionsC), vp]
+    L.ms_pairs.restype = i32
+    L.ms_radix_sort.argtypes = [vp, vp, vp, vp, sz, u32, vp, sz, ctypes.POINTER(OptionsC), vp]
+    L.ms_radix_sort.restype = i32
+    L.ms_batched.argtypes = [vp, vp, vp, vp, vp, u32, sz, u32, ctypes.POINTER(BucketFnC), vp, vp,
+                             sz, ctypes.POINTER(OptionsC), vp]
+    L.ms_batched.restype = i32
+    L.ms_learned_fit.argtypes = [vp, sz, vp, u32, vp, vp, sz, vp]
+    L.ms_learned_fit.restype = i32
+    L.ms_copy_u32.argtypes = [vp, vp, sz, vp]
+    L.ms_copy_u32.restype = i32
+    _lib = L
+    return L
+
+
+def _check(rc, what):
+    if rc != MS_OK:
+        raise MultisplitError(rc, what)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    import torch
+    if not t.is_cuda:
+        raise ValueError("tensor must be on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _u32(t, name):
+    if t is None:
+        return None
+    if t.element_size() != 4:
+        raise ValueError("%s must hold 32-bit elements" % name)
+    return _ptr(t)
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class BucketFn:
+    """Bucket identifier descriptor (MS_BUCKET_*)."""
+
+    def __init__(self, kind, shift=0, mask=0, divisor=0, splitters=None, model=None):
+        self.kind, self.shift, self.mask, self.divisor = kind, shift, mask, divisor
+        self.splitters, self.model = splitters, model
+
+    @staticmethod
+    def shift_mask(shift, mask):
+        return BucketFn(BUCKET_SHIFT_MASK, shift=shift, mask=mask)
+
+    @staticmethod
+    def div(divisor):
+        return BucketFn(BUCKET_DIV, divisor=divisor)
+
+    @staticmethod
+    def splitter(splitters):
+        return BucketFn(BUCKET_SPLITTERS, splitters=splitters)
+
+    @staticmethod
+    def learned(splitters, model):
+        return BucketFn(BUCKET_LEARNED, splitters=splitters, model=model)
+
+    def c(self):
+        return BucketFnC(self.kind, self.shift, self.mask, self.divisor,
+                         _u32(self.splitters, "splitters"),
+                         _ptr(self.model) if self.model is not None else None)
+
+
+class Options:
+    """Tuning and instrumentation (ms_options); all fields optional."""
+
+    def __init__(self, reorder=0, waves_per_block=0, items_per_lane=0, max_chunks=0,
+                 stage_events=None, mispredicts=None):
+        self.reorder, self.waves_per_block = reorder, waves_per_block
+        self.items_per_lane, self.max_chunks = items_per_lane, max_chunks
+        self.stage_events = stage_events   # list of 4 torch.cuda.Event or None
+        self.mispredicts = mispredicts     # 1-element int64 CUDA tensor or None
+        self._ev = None
+
+    def c(self):
+        ev = None
+        if self.stage_events is not None:
+            self._ev = (ctypes.c_void_p * 4)(*[e.cuda_event for e in self.stage_events])
+            ev = ctypes.cast(self._ev, ctypes.c_void_p)
+        return OptionsC(self.reorder, self.waves_per_block, self.items_per_lane,
+                        self.max_chunks, ev, _ptr(self.mispredicts))
+
+
+def _opt(options):
+    return ctypes.byref(options.c()) if options is not None else None
+
+
+def workspace_size(op, n, m, num_inst=0, options=None):
+    return int(lib().ms_workspace_size(op, n, m, num_inst, _opt(options)))
+
+
+def _workspace(op, n, m, device, options=None, num_inst=0, ws=None):
+    import torch
+    need = workspace_size(op, n, m, num_inst, options)
+    if need == 0 and n > 0:
+        raise MultisplitError(-1, "ms_workspace_size")
+    if ws is not None:
+        return ws, ws.numel() * ws.element_size()
+    return torch.empty(max(need, 256), dtype=torch.uint8, device=device), max(need, 256)
+
+
+def keys(keys_in, m, fn, keys_out=None, offsets=None, options=None, stream=None, ws=None):
+    """Stable multisplit of a 32-bit key tensor.  Returns (keys_out, offsets)."""
+    import torch
+    n = keys_in.numel()
+    if keys_out is None:
+        keys_out = torch.empty_like(keys_in)
+    if offsets is None:
+        offsets = torch.empty(m + 1, dtype=torch.int32, device=keys_in.device)
+    w, wb = _workspace(OP_KEYS, n, m, keys_in.device, options, ws=ws)
+    f = fn.c()
+    o = options.c() if options is not None else None
+    rc = lib().ms_keys(_u32(keys_in, "keys_in"), _u32(keys_out, "keys_out"),
+                       _u32(offsets, "offsets"), n, m, ctypes.byref(f), _ptr(w), wb,
+                       ctypes.byref(o) if o is not None else None, _stream(stream))
+    _check(rc, "ms_keys")
+    return keys_out, offsets
+
+
+def pairs(keys_in, vals_in, m, fn, keys_out=None, vals_out=None, offsets=None, options=None,
+          stream=None, ws=None):
+    """Stable multisplit of key-value pairs.  Returns (keys_out, vals_out, offsets)."""
+    import torch
+    n = keys_in.numel()
+    if vals_in.numel() != n:
+        raise ValueError("keys and values differ in length")
+    if keys_out is None:
+        keys_out = torch.empty_like(keys_in)
+    if vals_out is None:
+        vals_out = torch.empty_like(vals_in)
+    if offsets is None:
+        offsets = torch.empty(m + 1, dtype=torch.int32, device=keys_in.device)
+    w, wb = _workspace(OP_PAIRS, n, m, keys_in.device, options, ws=ws)
+    f = fn.c()
+    o = options.c() if options is not None else None
+    rc = lib().ms_pairs(_u32(keys_in, "keys_in"), _u32(vals_in, "vals_in"),
+                        _u32(keys_out, "keys_out"), _u32(vals_out, "vals_out"),
+                        _u32(offsets, "offsets"), n, m, ctypes.byref(f), _ptr(w), wb,
+                        ctypes.byref(o) if o is not None else None, _stream(stream))
+    _check(rc, "ms_pairs")
+    return keys_out, vals_out, offsets
+
+
+def radix_sort(keys_in, vals_in=None, bits_per_pass=8, keys_out=None, vals_out=None,
+               options=None, stream=None, ws=None):
+    """LSD radix sort from multisplit passes.  Returns (keys_out, vals_out or None)."""
+    import torch
+    n = keys_in.numel()
+    kv = vals_in is not None
+    if keys_out is None:
+        keys_out = torch.empty_like(keys_in)
+    if kv and vals_out is None:
+        vals_out = torch.empty_like(vals_in)
+    w, wb = _workspace(OP_RADIX_SORT_PAIRS if kv else OP_RADIX_SORT, n, 256, keys_in.device,
+                       options, ws=ws)
+    o = options.c() if options is not None else None
+    rc = lib().ms_radix_sort(_u32(keys_in, "keys_in"), _u32(vals_in, "vals_in"),
+                             _u32(keys_out, "keys_out"), _u32(vals_out, "vals_out"), n,
+                             bits_per_pass, _ptr(w), wb,
+                             ctypes.byref(o) if o is not None else None, _stream(stream))
+    _check(rc, "ms_radix_sort")
+    return keys_out, vals_out
+
+
+def copy_u32(dst, src, stream=None):
+    rc = lib().ms_copy_u32(_u32(dst, "dst"), _u32(src, "src"), src.numel(), _stream(stream))
+    _check(rc, "ms_copy_u32")
+    return dst

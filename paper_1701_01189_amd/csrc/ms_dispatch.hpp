@@ -1,0 +1,136 @@
+// Launch-time selection of kernel instantiations: bucket kind, ballot rounds
+// (BITS = ceil(log2 m)), key-only or key-value, workgroup shape and
+// reordering mode are all template parameters of the kernels, so the inner
+// loops carry no run-time branches.  One translation unit per bucket kind
+// instantiates its share (ms_kind_*.hip).
+#pragma once
+
+#include "ms_kernels.hpp"
+
+namespace ms {
+
+struct PreArgs {
+  const uint32_t* keys;
+  Plan plan;
+  BucketParams bp;
+  uint32_t* H;
+  int mode;
+  hipStream_t stream;
+};
+
+struct PostArgs {
+  const uint32_t* keys_in;
+  const uint32_t* vals_in;
+  uint32_t* keys_out;
+  uint32_t* vals_out;
+  const uint32_t* G;
+  const uint32_t* totals;
+  uint32_t* offsets;
+  Plan plan;
+  BucketParams bp;
+  int mode, wpb, nw;
+  bool kv;
+  hipStream_t stream;
+};
+
+// Shapes with an instantiated post-scan: (mode, waves per block, windows).
+inline bool post_shape_supported(int mode, int wpb, int nw) {
+  if (mode == kBlock)
+    return (wpb == 8 && (nw == 4 || nw == 8)) || (wpb == 4 && (nw == 8 || nw == 16));
+  if (mode == kWaveMode) return (wpb == 8 && nw == 8) || (wpb == 4 && nw == 16);
+  if (mode == kDirect) return wpb == 8 && nw == 8;
+  return false;
+}
+
+// Pre-scan workgroups are always 8 wavefronts: BMS chunks are shared by the
+// whole workgroup, WMS/DMS chunks belong to single wavefronts.
+constexpr int kPreWaves = 8;
+
+template <int Kind, int BITS>
+hipError_t pre_launch(const PreArgs& a) {
+  if (a.mode == kBlock) {
+    hipLaunchKernelGGL((prescan_kernel<Kind, BITS, kPreWaves, kPreWaves>), dim3(a.plan.L0),
+                       dim3(kPreWaves * kWave), 0, a.stream, a.keys, a.plan, a.bp, a.H);
+  } else {
+    hipLaunchKernelGGL((prescan_kernel<Kind, BITS, kPreWaves, 1>),
+                       dim3((a.plan.L0 + kPreWaves - 1) / kPreWaves), dim3(kPreWaves * kWave), 0,
+                       a.stream, a.keys, a.plan, a.bp, a.H);
+  }
+  return hipGetLastError();
+}
+
+template <int Kind>
+hipError_t pre_dispatch(const PreArgs& a, int bits) {
+  switch (bits) {
+    case 0: return pre_launch<Kind, 0>(a);
+    case 1: return pre_launch<Kind, 1>(a);
+    case 2: return pre_launch<Kind, 2>(a);
+    case 3: return pre_launch<Kind, 3>(a);
+    case 4: return pre_launch<Kind, 4>(a);
+    case 5: return pre_launch<Kind, 5>(a);
+    case 6: return pre_launch<Kind, 6>(a);
+    case 7: return pre_launch<Kind, 7>(a);
+    case 8: return pre_launch<Kind, 8>(a);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int Kind, int BITS, bool KV, int WPB, int NW, int MODE>
+hipError_t post_launch(const PostArgs& a) {
+  constexpr int WPG = (MODE == kBlock) ? WPB : 1;
+  constexpr int GPB = WPB / WPG;
+  dim3 grid((a.plan.L0 + GPB - 1) / GPB), block(WPB * kWave);
+  hipLaunchKernelGGL((postscan_kernel<Kind, BITS, KV, WPB, NW, MODE>), grid, block, 0, a.stream,
+                     a.keys_in, a.vals_in, a.keys_out, a.vals_out, a.G, a.totals, a.offsets,
+                     a.plan, a.bp);
+  return hipGetLastError();
+}
+
+template <int Kind, int BITS, bool KV>
+hipError_t post_shape(const PostArgs& a) {
+  if (a.mode == kBlock) {
+    if (a.wpb == 8 && a.nw == 8) return post_launch<Kind, BITS, KV, 8, 8, kBlock>(a);
+    if (a.wpb == 8 && a.nw == 4) return post_launch<Kind, BITS, KV, 8, 4, kBlock>(a);
+    if (a.wpb == 4 && a.nw == 8) return post_launch<Kind, BITS, KV, 4, 8, kBlock>(a);
+    if (a.wpb == 4 && a.nw == 16) return post_launch<Kind, BITS, KV, 4, 16, kBlock>(a);
+  } else if (a.mode == kWaveMode) {
+    if (a.wpb == 8 && a.nw == 8) return post_launch<Kind, BITS, KV, 8, 8, kWaveMode>(a);
+    if (a.wpb == 4 && a.nw == 16) return post_launch<Kind, BITS, KV, 4, 16, kWaveMode>(a);
+  } else if (a.mode == kDirect) {
+    if (a.wpb == 8 && a.nw == 8) return post_launch<Kind, BITS, KV, 8, 8, kDirect>(a);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int Kind, int BITS>
+hipError_t post_kv(const PostArgs& a) {
+  return a.kv ? post_shape<Kind, BITS, true>(a) : post_shape<Kind, BITS, false>(a);
+}
+
+template <int Kind>
+hipError_t post_dispatch(const PostArgs& a, int bits) {
+  switch (bits) {
+    case 0: return post_kv<Kind, 0>(a);
+    case 1: return post_kv<Kind, 1>(a);
+    case 2: return post_kv<Kind, 2>(a);
+    case 3: return post_kv<Kind, 3>(a);
+    case 4: return post_kv<Kind, 4>(a);
+    case 5: return post_kv<Kind, 5>(a);
+    case 6: return post_kv<Kind, 6>(a);
+    case 7: return post_kv<Kind, 7>(a);
+    case 8: return post_kv<Kind, 8>(a);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// Entry points defined in the per-kind translation units.
+hipError_t pre_shift_mask(const PreArgs& a, int bits);
+hipError_t pre_div(const PreArgs& a, int bits);
+hipError_t pre_splitters(const PreArgs& a, int bits);
+hipError_t pre_learned(const PreArgs& a, int bits);
+hipError_t post_shift_mask(const PostArgs& a, int bits);
+hipError_t post_div(const PostArgs& a, int bits);
+hipError_t post_splitters(const PostArgs& a, int bits);
+hipError_t post_learned(const PostArgs& a, int bits);
+
+}  // namespace ms

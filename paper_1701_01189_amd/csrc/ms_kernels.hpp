@@ -1,0 +1,358 @@
+// gfx950 kernels of the three-stage multisplit (Section 4.6: pre-scan, scan,
+// post-scan) with wavefront-level (WMS), block-level (BMS) or no (DMS)
+// reordering (Sections 5.3 and 5.6).
+//
+// Vocabulary (Section 5.3): a *window* is 64 consecutive elements ranked by
+// one wavefront with ballots; a *tile* is the set of windows reordered
+// together in LDS (one wavefront's NW windows for WMS, all wavefronts' for
+// BMS); a *chunk* is a run of consecutive tiles owned by one group (a
+// wavefront for WMS/DMS, a workgroup for BMS) -- one column of H.
+#pragma once
+
+#include "ms_device.hpp"
+
+namespace ms {
+
+enum Mode { kBlock = 1, kWaveMode = 2, kDirect = 3 };
+
+struct Plan {
+  uint32_t n;         // elements
+  uint32_t m;         // buckets
+  uint32_t L0;        // chunks = columns of H
+  uint32_t chunk;     // elements per chunk (multiple of the tile size)
+  uint32_t tile;      // elements per tile
+};
+
+// ---------------------------------------------------------------------------
+// group barriers: a whole workgroup (BMS) or a single wavefront (WMS/DMS)
+// ---------------------------------------------------------------------------
+template <int WPG>
+__device__ __forceinline__ void group_sync() {
+  if (WPG > 1) {
+    __syncthreads();
+  } else {
+    // one wavefront: LDS operations of a wavefront complete in order; only
+    // the compiler has to be kept from moving accesses across this point.
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+}
+
+// Exclusive scan of one value per thread over a group of WPG wavefronts.
+// `tmp` holds WPG words of LDS private to the group.  Returns the exclusive
+// prefix; *total receives the group total.
+template <int WPG>
+__device__ __forceinline__ uint32_t group_exclusive_scan(uint32_t v, uint32_t* tmp, uint32_t wg,
+                                                         uint32_t lane, uint32_t* total) {
+  uint32_t inc = wave_inclusive_scan(v, lane);
+  if (WPG == 1) {
+    *total = wave_broadcast(inc, kWave - 1);
+    return inc - v;
+  }
+  if (lane == kWave - 1) tmp[wg] = inc;
+  group_sync<WPG>();
+  uint32_t before = 0, all = 0;
+#pragma unroll
+  for (int w = 0; w < WPG; ++w) {
+    uint32_t t = tmp[w];
+    before += (w < (int)wg) ? t : 0u;
+    all += t;
+  }
+  group_sync<WPG>();  // tmp may be reused right after
+  *total = all;
+  return before + inc - v;
+}
+
+// ---------------------------------------------------------------------------
+// Pre-scan: one column of H per chunk (Algorithm 1's pre-scan with the
+// window histogram of Algorithm 2).  WPG wavefronts share a chunk; a
+// workgroup of WPB wavefronts serves WPB / WPG chunks.  Order inside a chunk
+// does not matter for a histogram, so wavefronts stride over its windows.
+// H is bucket-major: H[b * L0 + c].
+// ---------------------------------------------------------------------------
+template <int Kind, int BITS, int WPB, int WPG>
+__global__ void __launch_bounds__(WPB* kWave)
+prescan_kernel(const uint32_t* __restrict__ keys, Plan plan, BucketParams bp,
+               uint32_t* __restrict__ H) {
+  constexpr int GPB = WPB / WPG;
+  constexpr int MB = Owned<BITS>::value;
+  constexpr int U = 16;  // windows in flight per wavefront
+  __shared__ BucketLds tables;
+  __shared__ uint32_t s_hist[(WPG > 1) ? WPB * kMaxBuckets : 1];
+  stage_bucket_tables<Kind>(bp, &tables);
+  __syncthreads();
+  Bucket<Kind, BITS> bf(bp, &tables);
+
+  const uint32_t lane = lane_id();
+  const uint32_t w = threadIdx.x / kWave;
+  const uint32_t g = w / WPG, wg = w % WPG;
+  const uint32_t c = (GPB == 1 ? xcd_chunk(blockIdx.x, gridDim.x) : blockIdx.x * GPB + g);
+  uint32_t cnt[MB];
+#pragma unroll
+  for (int t = 0; t < MB; ++t) cnt[t] = 0;
+
+  if (c < plan.L0) {
+    const uint32_t c0 = c * plan.chunk;
+    const uint32_t len = min(plan.chunk, plan.n - c0);
+    const uint32_t groups = (uint32_t)(((uint64_t)len + U * kWave - 1) / (U * kWave));
+    for (uint32_t gi = wg; gi < groups; gi += WPG) {
+      const uint32_t base = c0 + gi * (U * kWave);
+      const uint32_t rem = len - gi * (U * kWave);
+      if (rem >= (uint32_t)(U * kWave)) {
+        uint32_t k[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) k[u] = keys[base + u * kWave + lane];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          window_histogram<BITS>(bf(k[u]), true, ~0ull, lane, cnt);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      } else {
+        for (int u = 0; u < U; ++u) {
+          const uint32_t off = u * kWave + lane;
+          const bool valid = off < rem;
+          uint32_t kk = valid ? keys[base + off] : 0u;
+          uint32_t b = valid ? bf(kk) : 0u;
+          window_histogram<BITS>(b, valid, ballot(valid), lane, cnt);
+        }
+      }
+    }
+  }
+  if (WPG == 1) {
+    if (c < plan.L0) {
+#pragma unroll
+      for (int t = 0; t < MB; ++t) {
+        uint32_t b = lane + kWave * t;
+        if (b < plan.m) H[b * plan.L0 + c] = cnt[t];
+      }
+    }
+  } else {
+#pragma unroll
+    for (int t = 0; t < MB; ++t) {
+      uint32_t b = lane + kWave * t;
+      if (b < plan.m) s_hist[w * kMaxBuckets + b] = cnt[t];
+    }
+    __syncthreads();
+    if (c < plan.L0) {
+      for (uint32_t b = threadIdx.x; b < plan.m; b += WPB * kWave) {
+        uint32_t s = 0;
+#pragma unroll
+        for (int ww = 0; ww < WPB; ++ww) s += s_hist[ww * kMaxBuckets + b];
+        H[b * plan.L0 + c] = s;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Post-scan (Algorithm 1's post-scan, Sections 5.5.3-5.6).
+//
+// For every tile of the group's chunk:
+//  1. each wavefront loads NW windows, element (wave wg, window j, lane l) at
+//     tile_base + (wg*NW + j)*64 + l -- so (wg, j, l) is input order;
+//  2. per window: match mask of the lane's bucket (Algorithm 3), rank among
+//     lower lanes, and a per-wavefront running count per bucket kept in LDS
+//     (the highest lane of each bucket publishes the new count): the first
+//     and second terms of Eq. (4);
+//  3. one exclusive scan over the bucket-major table [bucket][wavefront] of
+//     those counts gives, for wavefront wg and bucket b, the number of tile
+//     elements in buckets < b plus those of bucket b in earlier wavefronts --
+//     the tile-local destination base (third term of Eq. 4 plus the tile
+//     histogram scan of Section 5.6.2);
+//  4. write the element into its slot of the reorder buffer (a stable local
+//     multisplit of the tile, Section 4.7);
+//  5. read the buffer linearly; slot q of bucket b goes to
+//     G[b][chunk] + (elements of b in earlier tiles) + (q - tile start of b).
+// Mode kDirect skips 3-5 and writes from registers (DMS).
+// ---------------------------------------------------------------------------
+template <int Kind, int BITS, bool KV, int WPB, int NW, int MODE>
+__global__ void __launch_bounds__(WPB* kWave)
+postscan_kernel(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
+                uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
+                const uint32_t* __restrict__ G, const uint32_t* __restrict__ totals,
+                uint32_t* __restrict__ offsets, Plan plan, BucketParams bp) {
+  constexpr int WPG = (MODE == kBlock) ? WPB : 1;
+  constexpr int GPB = WPB / WPG;
+  constexpr int T = WPG * NW * kWave;
+  constexpr bool REORDER = (MODE != kDirect);
+  constexpr int CNT_STRIDE = kMaxBuckets + 1;
+
+  __shared__ BucketLds tables;
+  __shared__ uint32_t s_cnt[WPB * CNT_STRIDE];           // per wavefront counts
+  __shared__ uint32_t s_run[GPB * kMaxBuckets];          // running output base
+  __shared__ uint32_t s_delta[REORDER ? GPB * kMaxBuckets : 1];
+  __shared__ uint32_t s_keys[REORDER ? GPB * T : 1];
+  __shared__ uint32_t s_vals[(REORDER && KV) ? GPB * T : 1];
+  __shared__ uint8_t s_bk[REORDER ? GPB * T : 1];
+  __shared__ uint32_t s_tmp[WPB];
+
+  const uint32_t lane = lane_id();
+  const uint32_t w = threadIdx.x / kWave;
+  const uint32_t g = w / WPG, wg = w % WPG;
+  const uint32_t tid_g = wg * kWave + lane;
+  const uint32_t m = plan.m;
+
+  stage_bucket_tables<Kind>(bp, &tables);
+
+  // Bucket bases: exclusive scan of the bucket totals (first term of Eq. 2),
+  // computed by every workgroup.  m <= 256 <= threads per workgroup.
+  {
+    uint32_t v = threadIdx.x < m ? totals[threadIdx.x] : 0u;
+    uint32_t total;
+    uint32_t pre = group_exclusive_scan<WPB>(v, s_tmp, w, lane, &total);
+    __syncthreads();
+    if (threadIdx.x < m) {
+      s_cnt[threadIdx.x] = pre;  // staged bucket base
+      if (blockIdx.x == 0) offsets[threadIdx.x] = pre;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) offsets[m] = plan.n;
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < GPB * m; i += WPB * kWave) {
+      uint32_t gg = i / m, b = i % m;
+      uint32_t cc = (GPB == 1 ? xcd_chunk(blockIdx.x, gridDim.x) : blockIdx.x * GPB + gg);
+      s_run[gg * kMaxBuckets + b] = (cc < plan.L0) ? s_cnt[b] + G[b * plan.L0 + cc] : 0u;
+    }
+    __syncthreads();
+  }
+
+  Bucket<Kind, BITS> bf(bp, &tables);
+  const uint32_t c = (GPB == 1 ? xcd_chunk(blockIdx.x, gridDim.x) : blockIdx.x * GPB + g);
+  if (c >= plan.L0) return;  // only whole idle groups leave (never a BMS group)
+  const uint32_t c0 = c * plan.chunk;
+  const uint32_t len = min(plan.chunk, plan.n - c0);
+  volatile uint32_t* my_cnt = s_cnt + w * CNT_STRIDE;
+  uint32_t* run = s_run + g * kMaxBuckets;
+
+  if (MODE == kDirect) {
+    // DMS: counters are the running output positions of this wavefront.
+    for (uint32_t b = lane; b < m; b += kWave) my_cnt[b] = run[b];
+    group_sync<1>();
+    const uint32_t steps = (uint32_t)(((uint64_t)len + NW * kWave - 1) / (NW * kWave));
+    for (uint32_t si = 0; si < steps; ++si) {
+      const uint32_t base = c0 + si * (NW * kWave);
+      const uint32_t rem = len - si * (NW * kWave);
+      uint32_t k[NW], v[NW];
+#pragma unroll
+      for (int j = 0; j < NW; ++j) {
+        const uint32_t off = j * kWave + lane;
+        const bool valid = off < rem;
+        k[j] = valid ? keys_in[base + off] : 0u;
+        if (KV) v[j] = valid ? vals_in[base + off] : 0u;
+      }
+#pragma unroll
+      for (int j = 0; j < NW; ++j) {
+        const bool valid = (uint32_t)(j * kWave) + lane < rem;
+        uint32_t b = valid ? bf(k[j]) : 0u;
+        uint64_t vm = ballot(valid);
+        uint64_t mm = match_bucket<BITS>(b, valid, vm);
+        uint32_t r = count_below(mm), cnt = popc64(mm);
+        uint32_t pos = my_cnt[b];
+        if (valid && r + 1 == cnt) my_cnt[b] = pos + cnt;
+        uint32_t o = pos + r;
+        if (valid && o < plan.n) {
+          keys_out[o] = k[j];
+          if (KV) vals_out[o] = v[j];
+        }
+      }
+    }
+  } else {
+    uint32_t* s_k = s_keys + g * T;
+    uint32_t* s_v = s_vals + (KV ? g * T : 0);
+    uint8_t* s_b = s_bk + g * T;
+    uint32_t* delta = s_delta + g * kMaxBuckets;
+    volatile uint32_t* grp_cnt = s_cnt + (g * WPG) * CNT_STRIDE;
+    const uint32_t ntiles = (uint32_t)(((uint64_t)len + T - 1) / T);
+    for (uint32_t ti = 0; ti < ntiles; ++ti) {
+      const uint32_t tb = c0 + ti * T;
+      const uint32_t tcount = min((uint32_t)T, len - ti * T);
+      for (uint32_t b = lane; b < m; b += kWave) my_cnt[b] = 0u;
+      uint32_t k[NW], v[NW], bk[NW], lr[NW];
+#pragma unroll
+      for (int j = 0; j < NW; ++j) {
+        const uint32_t off = (wg * NW + j) * kWave + lane;
+        const bool valid = off < tcount;
+        k[j] = valid ? __builtin_nontemporal_load(keys_in + tb + off) : 0u;
+        if (KV) v[j] = valid ? __builtin_nontemporal_load(vals_in + tb + off) : 0u;
+      }
+      group_sync<1>();
+      // ranking: Algorithm 3 per window + per-wavefront running counts
+#pragma unroll
+      for (int j = 0; j < NW; ++j) {
+        const bool valid = (wg * NW + j) * kWave + lane < tcount;
+        bk[j] = valid ? bf(k[j]) : 0u;
+        uint64_t vm = ballot(valid);
+        uint64_t mm = match_bucket<BITS>(bk[j], valid, vm);
+        uint32_t r = count_below(mm), cnt = popc64(mm);
+        uint32_t before = my_cnt[bk[j]];
+        lr[j] = before + r;
+        if (valid && r + 1 == cnt) my_cnt[bk[j]] = before + cnt;
+      }
+      group_sync<WPG>();
+      // exclusive scan of the bucket-major table: entry e = b*WPG + wave
+      {
+        const uint32_t E = m * WPG;
+        const uint32_t ept = (E + WPG * kWave - 1) / (WPG * kWave);
+        uint32_t e0 = tid_g * ept;
+        uint32_t vals[4];
+        uint32_t s = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          uint32_t e = e0 + i;
+          vals[i] = ((uint32_t)i < ept && e < E) ? grp_cnt[(e % WPG) * CNT_STRIDE + e / WPG] : 0u;
+          s += vals[i];
+        }
+        uint32_t total;
+        uint32_t pre = group_exclusive_scan<WPG>(s, s_tmp + g * WPG, wg, lane, &total);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          uint32_t e = e0 + i;
+          if ((uint32_t)i < ept && e < E) grp_cnt[(e % WPG) * CNT_STRIDE + e / WPG] = pre;
+          pre += vals[i];
+        }
+      }
+      group_sync<WPG>();
+      // tile bucket starts -> output delta; advance the running bases
+      for (uint32_t b = tid_g; b < m; b += WPG * kWave) {
+        uint32_t st = grp_cnt[b];
+        uint32_t nx = (b + 1 < m) ? grp_cnt[b + 1] : tcount;
+        delta[b] = run[b] - st;
+        run[b] += nx - st;
+      }
+      // local reorder: slot = tile base of (bucket, wavefront) + rank
+#pragma unroll
+      for (int j = 0; j < NW; ++j) {
+        if ((wg * NW + j) * kWave + lane < tcount) {
+          uint32_t slot = my_cnt[bk[j]] + lr[j];
+          s_k[slot] = k[j];
+          if (KV) s_v[slot] = v[j];
+          s_b[slot] = (uint8_t)bk[j];
+        }
+      }
+      group_sync<WPG>();
+      // coalesced write-back: consecutive slots of a bucket are consecutive
+      // output positions
+#pragma unroll
+      for (int j = 0; j < NW; ++j) {
+        uint32_t q = j * (WPG * kWave) + tid_g;
+        if (q < tcount) {
+          uint32_t b = s_b[q];
+          uint32_t o = delta[b] + q;
+          if (o < plan.n) {
+            keys_out[o] = s_k[q];
+            if (KV) vals_out[o] = s_v[q];
+          }
+        }
+      }
+      group_sync<WPG>();
+    }
+  }
+  if (Kind == kLearned && bp.mispredicts) {
+    uint32_t miss = bf.misses();
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) miss += __shfl_xor(miss, d, kWave);
+    if (lane == 0 && miss) atomicAdd(bp.mispredicts, (unsigned long long)miss);
+  }
+}
+
+}  // namespace ms

@@ -1,0 +1,400 @@
+// Host dispatch and C ABI of the gfx950 multisplit library.
+//
+// Implements include/multisplit.h: argument validation (before any HIP call),
+// work planning (tile and chunk sizes, the number of subproblems L0 of
+// Section 4.4), workspace carving and the stream-ordered launch sequence
+// pre-scan -> scan -> post-scan of Section 4.6 (Algorithm 1).
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+#include <string.h>
+
+#include "../../include/multisplit.h"
+#include "ms_aux_kernels.hpp"
+#include "ms_dispatch.hpp"
+
+namespace {
+
+using ms::BucketParams;
+using ms::Plan;
+
+constexpr uint32_t kNumCUs = 256;        // MI355X compute units
+constexpr uint32_t kLdsPerCU = 160 * 1024;
+constexpr size_t kWsAlign = 256;
+
+struct Shape {
+  int mode;     // ms::kBlock / kWaveMode / kDirect
+  int wpb;      // wavefronts per workgroup
+  int nw;       // windows per wavefront per tile
+  uint32_t max_chunks;
+};
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+uint32_t ceil_log2(uint32_t m) {
+  uint32_t b = 0;
+  while ((1u << b) < m) ++b;
+  return b;
+}
+
+bool shape_supported(const Shape& s) { return ms::post_shape_supported(s.mode, s.wpb, s.nw); }
+
+// Default: block-level reordering (BMS), 8 wavefronts x 8 windows, which
+// holds 4096 elements per tile; the paper's own defaults are 8 warps x 4
+// windows of 32 (Section 6, "Parameters").
+int resolve_shape(const ms_options* opt, Shape* s) {
+  s->mode = ms::kBlock;
+  s->wpb = 8;
+  s->nw = 8;
+  s->max_chunks = 0;
+  if (opt) {
+    if (opt->reorder < 0 || opt->reorder > MS_REORDER_NONE) return MS_ERR_INVALID_ARG;
+    if (opt->reorder == MS_REORDER_BLOCK) s->mode = ms::kBlock;
+    if (opt->reorder == MS_REORDER_WAVE) s->mode = ms::kWaveMode;
+    if (opt->reorder == MS_REORDER_NONE) s->mode = ms::kDirect;
+    if (opt->waves_per_block) s->wpb = opt->waves_per_block;
+    if (opt->items_per_lane) s->nw = opt->items_per_lane;
+    if (opt->max_chunks < 0) return MS_ERR_INVALID_ARG;
+    s->max_chunks = (uint32_t)opt->max_chunks;
+  }
+  return shape_supported(*s) ? MS_OK : MS_ERR_UNSUPPORTED;
+}
+
+// Static LDS of one post-scan workgroup (mirrors the kernel's arrays); used
+// to estimate how many workgroups are resident per compute unit.
+size_t post_lds_bytes(const Shape& s, bool kv) {
+  int wpg = s.mode == ms::kBlock ? s.wpb : 1;
+  int gpb = s.wpb / wpg;
+  size_t T = (size_t)wpg * s.nw * ms::kWave;
+  bool reorder = s.mode != ms::kDirect;
+  size_t b = sizeof(ms::BucketLds) + (size_t)s.wpb * (ms::kMaxBuckets + 1) * 4 +
+             (size_t)gpb * ms::kMaxBuckets * 4 + (size_t)s.wpb * 4;
+  if (reorder) b += (size_t)gpb * ms::kMaxBuckets * 4 + (size_t)gpb * T * (4 + (kv ? 4 : 0) + 1);
+  return b;
+}
+
+// Subproblems: chunks of consecutive tiles, about one per resident group so
+// that H stays small (Section 4.4: few first-level subproblems, large local
+// ones).
+Plan make_plan(size_t n, uint32_t m, const Shape& s, bool kv) {
+  Plan p;
+  p.n = (uint32_t)n;
+  p.m = m;
+  int wpg = s.mode == ms::kBlock ? s.wpb : 1;
+  p.tile = (uint32_t)(wpg * s.nw * ms::kWave);
+  uint64_t tiles = (n + p.tile - 1) / p.tile;
+  uint32_t cap = s.max_chunks;
+  if (cap == 0) {
+    size_t lds = post_lds_bytes(s, kv);
+    uint32_t by_lds = (uint32_t)(kLdsPerCU / lds);
+    uint32_t by_waves = 32u / (uint32_t)s.wpb;
+    uint32_t blocks = by_lds < by_waves ? by_lds : by_waves;
+    if (blocks < 1) blocks = 1;
+    cap = kNumCUs * blocks * (uint32_t)(s.wpb / wpg);
+  }
+  uint64_t L0 = tiles < cap ? tiles : cap;
+  if (L0 == 0) L0 = 1;
+  uint64_t tpc = (tiles + L0 - 1) / L0;
+  if (tpc == 0) tpc = 1;
+  L0 = (tiles + tpc - 1) / tpc;
+  if (L0 == 0) L0 = 1;
+  p.L0 = (uint32_t)L0;
+  p.chunk = (uint32_t)(tpc * p.tile);
+  return p;
+}
+
+// Workspace: [bucket totals (256) | spare offsets (257)] then H (m x L0).
+constexpr size_t kWsHeader = ((ms::kMaxBuckets + ms::kMaxBuckets + 1) * 4 + kWsAlign - 1) / kWsAlign * kWsAlign;
+
+size_t ms_ws_bytes(const Plan& p) {
+  return kWsHeader + align_up((size_t)p.m * p.L0 * 4, kWsAlign);
+}
+
+struct Workspace {
+  uint32_t* totals;
+  uint32_t* H;
+};
+
+Workspace carve(void* ws, const Plan& p) {
+  Workspace w;
+  char* b = (char*)ws;
+  w.totals = (uint32_t*)b;
+  w.H = (uint32_t*)(b + kWsHeader);
+  return w;
+}
+
+// Granlund-Montgomery constants for floor(k / d), 32-bit unsigned.
+void div_magic(uint32_t d, uint32_t* magic, uint32_t* sh1, uint32_t* sh2) {
+  uint32_t l = ceil_log2(d);
+  unsigned __int128 num = ((unsigned __int128)1 << 32) * (((unsigned __int128)1 << l) - d);
+  *magic = (uint32_t)(num / d + 1);
+  *sh1 = l < 1 ? l : 1;
+  *sh2 = l >= 1 ? l - 1 : 0;
+}
+
+int validate_fn(const ms_bucket_fn* fn, uint32_t m) {
+  if (!fn) return MS_ERR_INVALID_ARG;
+  switch (fn->kind) {
+    case MS_BUCKET_SHIFT_MASK:
+      if (fn->shift > 31) return MS_ERR_INVALID_ARG;
+      if (fn->mask > m - 1) return MS_ERR_BUCKET_RANGE;
+      return MS_OK;
+    case MS_BUCKET_DIV:
+      if (fn->divisor == 0) return MS_ERR_INVALID_ARG;
+      if (0xFFFFFFFFu / fn->divisor > m - 1) return MS_ERR_BUCKET_RANGE;
+      return MS_OK;
+    case MS_BUCKET_SPLITTERS:
+      if (m > 1 && !fn->splitters) return MS_ERR_INVALID_ARG;
+      return MS_OK;
+    case MS_BUCKET_LEARNED:
+      if ((m > 1 && !fn->splitters) || !fn->model) return MS_ERR_INVALID_ARG;
+      return MS_OK;
+    default:
+      return MS_ERR_INVALID_ARG;
+  }
+}
+
+BucketParams make_params(const ms_bucket_fn* fn, uint32_t m, uint64_t* mispredicts) {
+  BucketParams bp;
+  memset(&bp, 0, sizeof(bp));
+  bp.m = m;
+  bp.shift = fn->shift;
+  bp.mask = fn->mask;
+  if (fn->kind == MS_BUCKET_DIV) div_magic(fn->divisor, &bp.magic, &bp.sh1, &bp.sh2);
+  bp.splitters = fn->splitters;
+  bp.model = fn->model;
+  bp.mispredicts = (unsigned long long*)mispredicts;
+  return bp;
+}
+
+bool overlaps(const void* a, const void* b, size_t bytes) {
+  if (!a || !b) return false;
+  const char* x = (const char*)a;
+  const char* y = (const char*)b;
+  return x < y + bytes && y < x + bytes;
+}
+
+hipError_t pre_by_kind(int kind, const ms::PreArgs& a, int bits) {
+  switch (kind) {
+    case MS_BUCKET_SHIFT_MASK: return ms::pre_shift_mask(a, bits);
+    case MS_BUCKET_DIV: return ms::pre_div(a, bits);
+    case MS_BUCKET_SPLITTERS: return ms::pre_splitters(a, bits);
+    default: return ms::pre_learned(a, bits);
+  }
+}
+
+hipError_t post_by_kind(int kind, const ms::PostArgs& a, int bits) {
+  switch (kind) {
+    case MS_BUCKET_SHIFT_MASK: return ms::post_shift_mask(a, bits);
+    case MS_BUCKET_DIV: return ms::post_div(a, bits);
+    case MS_BUCKET_SPLITTERS: return ms::post_splitters(a, bits);
+    default: return ms::post_learned(a, bits);
+  }
+}
+
+hipError_t record(const ms_options* opt, int i, hipStream_t st) {
+  if (opt && opt->stage_events && opt->stage_events[i])
+    return hipEventRecord((hipEvent_t)opt->stage_events[i], st);
+  return hipSuccess;
+}
+
+hipError_t fill(uint32_t* p, uint32_t n, uint32_t v, hipStream_t st) {
+  if (!p || !n) return hipSuccess;
+  hipLaunchKernelGGL(ms::fill_u32_kernel, dim3((n + 255) / 256), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+// The three stages for one multisplit on already validated arguments.
+ms_status run_multisplit(const uint32_t* ki, const uint32_t* vi, uint32_t* ko, uint32_t* vo,
+                         uint32_t* offsets, size_t n, uint32_t m, const ms_bucket_fn* fn,
+                         void* ws, const Shape& s, const ms_options* opt, hipStream_t st) {
+  const bool kv = vi != nullptr;
+  if (n == 0) {
+    if (fill(offsets, m + 1, 0, st) != hipSuccess) return MS_ERR_HIP;
+    return MS_OK;
+  }
+  Plan p = make_plan(n, m, s, kv);
+  Workspace w = carve(ws, p);
+  BucketParams bp = make_params(fn, m, opt ? opt->d_mispredicts : nullptr);
+  const int bits = (int)ceil_log2(m);
+  if (record(opt, 0, st) != hipSuccess) return MS_ERR_HIP;
+  ms::PreArgs pa{ki, p, bp, w.H, s.mode, st};
+  if (pre_by_kind(fn->kind, pa, bits) != hipSuccess) return MS_ERR_HIP;
+  if (record(opt, 1, st) != hipSuccess) return MS_ERR_HIP;
+  hipLaunchKernelGGL(ms::scan_rows_kernel, dim3(m), dim3(ms::kScanThreads), 0, st, w.H, p.L0,
+                     w.totals);
+  if (hipGetLastError() != hipSuccess) return MS_ERR_HIP;
+  if (record(opt, 2, st) != hipSuccess) return MS_ERR_HIP;
+  // offsets are written by workgroup 0 of the post-scan; a NULL offsets
+  // pointer is redirected to the spare words after the bucket totals.
+  uint32_t* off = offsets ? offsets : w.totals + ms::kMaxBuckets;
+  ms::PostArgs qa{ki, vi, ko, vo, w.H, w.totals, off, p, bp, s.mode, s.wpb, s.nw, kv, st};
+  if (post_by_kind(fn->kind, qa, bits) != hipSuccess) return MS_ERR_HIP;
+  if (record(opt, 3, st) != hipSuccess) return MS_ERR_HIP;
+  return MS_OK;
+}
+
+ms_status check_common(const uint32_t* ki, const uint32_t* vi, const uint32_t* ko,
+                       const uint32_t* vo, size_t n, uint32_t m, bool kv) {
+  if (m < 1 || m > (uint32_t)ms::kMaxBuckets) return MS_ERR_INVALID_ARG;
+  if (n >= 0xFFFFFFFFull) return MS_ERR_INVALID_ARG;
+  if (n > 0) {
+    if (!ki || !ko) return MS_ERR_INVALID_ARG;
+    if (kv && (!vi || !vo)) return MS_ERR_INVALID_ARG;
+    size_t bytes = n * 4;
+    if (overlaps(ki, ko, bytes)) return MS_ERR_INVALID_ARG;
+    if (kv && (overlaps(vi, vo, bytes) || overlaps(ko, vo, bytes) || overlaps(ki, vo, bytes) ||
+               overlaps(vi, ko, bytes)))
+      return MS_ERR_INVALID_ARG;
+  }
+  return MS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ms_status_str(int status) {
+  switch (status) {
+    case MS_OK: return "MS_OK";
+    case MS_ERR_INVALID_ARG: return "MS_ERR_INVALID_ARG";
+    case MS_ERR_WORKSPACE: return "MS_ERR_WORKSPACE";
+    case MS_ERR_HIP: return "MS_ERR_HIP";
+    case MS_ERR_BUCKET_RANGE: return "MS_ERR_BUCKET_RANGE";
+    case MS_ERR_TIMEOUT: return "MS_ERR_TIMEOUT";
+    case MS_ERR_UNSUPPORTED: return "MS_ERR_UNSUPPORTED";
+    default: return "MS_ERR_UNKNOWN";
+  }
+}
+
+const char* ms_version(void) { return "multisplit-gfx950 0.1"; }
+
+size_t ms_workspace_size(int op, size_t n, uint32_t m, uint32_t num_inst, const ms_options* opt) {
+  (void)num_inst;
+  Shape s;
+  if (resolve_shape(opt, &s) != MS_OK) return 0;
+  switch (op) {
+    case MS_OP_KEYS:
+    case MS_OP_PAIRS: {
+      if (m < 1 || m > (uint32_t)ms::kMaxBuckets || n >= 0xFFFFFFFFull) return 0;
+      return ms_ws_bytes(make_plan(n, m, s, op == MS_OP_PAIRS));
+    }
+    case MS_OP_RADIX_SORT:
+    case MS_OP_RADIX_SORT_PAIRS: {
+      if (n >= 0xFFFFFFFFull) return 0;
+      bool kv = op == MS_OP_RADIX_SORT_PAIRS;
+      size_t data = align_up(n * 4, kWsAlign) * (kv ? 2 : 1);
+      return data + ms_ws_bytes(make_plan(n, 256, s, kv));
+    }
+    default:
+      return 0;
+  }
+}
+
+ms_status ms_keys(const uint32_t* d_keys_in, uint32_t* d_keys_out, uint32_t* d_offsets, size_t n,
+                  uint32_t m, const ms_bucket_fn* fn, void* d_ws, size_t ws_bytes,
+                  const ms_options* opt, void* stream) {
+  return ms_pairs(d_keys_in, nullptr, d_keys_out, nullptr, d_offsets, n, m, fn, d_ws, ws_bytes,
+                  opt, stream);
+}
+
+ms_status ms_pairs(const uint32_t* d_keys_in, const uint32_t* d_vals_in, uint32_t* d_keys_out,
+                   uint32_t* d_vals_out, uint32_t* d_offsets, size_t n, uint32_t m,
+                   const ms_bucket_fn* fn, void* d_ws, size_t ws_bytes, const ms_options* opt,
+                   void* stream) {
+  bool kv = d_vals_in != nullptr || d_vals_out != nullptr;
+  ms_status rc = check_common(d_keys_in, d_vals_in, d_keys_out, d_vals_out, n, m, kv);
+  if (rc != MS_OK) return rc;
+  int fr = validate_fn(fn, m);
+  if (fr != MS_OK) return (ms_status)fr;
+  Shape s;
+  int sr = resolve_shape(opt, &s);
+  if (sr != MS_OK) return (ms_status)sr;
+  size_t need = ms_workspace_size(kv ? MS_OP_PAIRS : MS_OP_KEYS, n, m, 0, opt);
+  if (n > 0 && (!d_ws || ws_bytes < need)) return MS_ERR_WORKSPACE;
+  return run_multisplit(d_keys_in, kv ? d_vals_in : nullptr, d_keys_out, d_vals_out, d_offsets,
+                        n, m, fn, d_ws, s, opt, (hipStream_t)stream);
+}
+
+ms_status ms_radix_sort(const uint32_t* d_keys_in, const uint32_t* d_vals_in,
+                        uint32_t* d_keys_out, uint32_t* d_vals_out, size_t n,
+                        uint32_t bits_per_pass, void* d_ws, size_t ws_bytes,
+                        const ms_options* opt, void* stream) {
+  bool kv = d_vals_in != nullptr || d_vals_out != nullptr;
+  if (bits_per_pass < 1 || bits_per_pass > 8) return MS_ERR_INVALID_ARG;
+  ms_status rc = check_common(d_keys_in, d_vals_in, d_keys_out, d_vals_out, n, 256, kv);
+  if (rc != MS_OK) return rc;
+  Shape s;
+  int sr = resolve_shape(opt, &s);
+  if (sr != MS_OK) return (ms_status)sr;
+  size_t need = ms_workspace_size(kv ? MS_OP_RADIX_SORT_PAIRS : MS_OP_RADIX_SORT, n, 256, 0, opt);
+  if (n > 0 && (!d_ws || ws_bytes < need)) return MS_ERR_WORKSPACE;
+  if (n == 0) return MS_OK;
+  hipStream_t st = (hipStream_t)stream;
+  char* b = (char*)d_ws;
+  uint32_t* tk = (uint32_t*)b;
+  b += align_up(n * 4, kWsAlign);
+  uint32_t* tv = nullptr;
+  if (kv) {
+    tv = (uint32_t*)b;
+    b += align_up(n * 4, kWsAlign);
+  }
+  void* ms_ws = b;
+  const uint32_t r = bits_per_pass;
+  const uint32_t passes = (32 + r - 1) / r;
+  // Ping-pong so that the last pass lands in the output buffers.
+  const uint32_t* src_k = d_keys_in;
+  const uint32_t* src_v = d_vals_in;
+  bool to_out = (passes % 2) == 1;
+  for (uint32_t pass = 0; pass < passes; ++pass) {
+    uint32_t shift = pass * r;
+    uint32_t width = (32 - shift) < r ? (32 - shift) : r;
+    uint32_t m = 1u << width;
+    ms_bucket_fn fn;
+    memset(&fn, 0, sizeof(fn));
+    fn.kind = MS_BUCKET_SHIFT_MASK;
+    fn.shift = shift;
+    fn.mask = m - 1;
+    uint32_t* dk = to_out ? d_keys_out : tk;
+    uint32_t* dv = to_out ? d_vals_out : tv;
+    ms_options o;
+    memset(&o, 0, sizeof(o));
+    if (opt) o = *opt;
+    o.stage_events = (pass == passes - 1 && opt) ? opt->stage_events : nullptr;
+    ms_status e = run_multisplit(src_k, kv ? src_v : nullptr, dk, kv ? dv : nullptr, nullptr, n, m,
+                                 &fn, ms_ws, s, &o, st);
+    if (e != MS_OK) return e;
+    src_k = dk;
+    src_v = dv;
+    to_out = !to_out;
+  }
+  return MS_OK;
+}
+
+ms_status ms_batched(const uint32_t* d_keys_in, const uint32_t* d_vals_in, uint32_t* d_keys_out,
+                     uint32_t* d_vals_out, const uint64_t* d_seg, uint32_t num_inst, size_t total,
+                     uint32_t m, const ms_bucket_fn* fn, uint32_t* d_offsets, void* d_ws,
+                     size_t ws_bytes, const ms_options* opt, void* stream) {
+  (void)d_keys_in; (void)d_vals_in; (void)d_keys_out; (void)d_vals_out; (void)d_seg;
+  (void)num_inst; (void)total; (void)m; (void)fn; (void)d_offsets; (void)d_ws; (void)ws_bytes;
+  (void)opt; (void)stream;
+  return MS_ERR_UNSUPPORTED;
+}
+
+ms_status ms_learned_fit(const uint32_t* d_sample, size_t n_sample, const uint32_t* d_splitters,
+                         uint32_t m, float* d_model, void* d_ws, size_t ws_bytes, void* stream) {
+  (void)d_sample; (void)n_sample; (void)d_splitters; (void)m; (void)d_model; (void)d_ws;
+  (void)ws_bytes; (void)stream;
+  return MS_ERR_UNSUPPORTED;
+}
+
+ms_status ms_copy_u32(uint32_t* d_dst, const uint32_t* d_src, size_t n, void* stream) {
+  if (n == 0) return MS_OK;
+  if (!d_dst || !d_src || overlaps(d_dst, d_src, n * 4)) return MS_ERR_INVALID_ARG;
+  if (((uintptr_t)d_dst | (uintptr_t)d_src) & 15) return MS_ERR_INVALID_ARG;
+  hipLaunchKernelGGL(ms::copy_u32_kernel, dim3(kNumCUs * 8), dim3(256), 0, (hipStream_t)stream,
+                     d_dst, d_src, n);
+  return hipGetLastError() == hipSuccess ? MS_OK : MS_ERR_HIP;
+}
+
+}  // extern "C"

@@ -1,0 +1,95 @@
+"""The C ABI library loads, exports every declared symbol, and rejects invalid
+arguments on the host before touching a GPU (runs without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "multisplit.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1701_01189_amd import binding, build
+    if build.stale():
+        build.build(force=True)
+    return binding.lib()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ms_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(L):
+    names = declared_functions()
+    assert "ms_keys" in names and "ms_pairs" in names and "ms_radix_sort" in names
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_status_strings(L):
+    assert L.ms_status_str(0) == b"MS_OK"
+    assert L.ms_status_str(-2) == b"MS_ERR_WORKSPACE"
+    assert L.ms_version().startswith(b"multisplit")
+
+
+def fake(addr):
+    return ctypes.c_void_p(addr)
+
+
+def test_host_validation_rejects_before_launch(L):
+    from paper_1701_01189_amd.binding import BucketFnC, OptionsC
+    fn = BucketFnC(0, 27, 31, 0, None, None)
+    ki, ko, ws = fake(0x1000000), fake(0x9000000), fake(0x20000000)
+    n = 1000
+    need = L.ms_workspace_size(0, n, 32, 0, None)
+    assert need > 0
+    # m out of range
+    assert L.ms_keys(ki, ko, None, n, 0, ctypes.byref(fn), ws, need, None, None) == -1
+    assert L.ms_keys(ki, ko, None, n, 257, ctypes.byref(fn), ws, need, None, None) == -1
+    # null pointers with n > 0, and overlapping in/out
+    assert L.ms_keys(None, ko, None, n, 32, ctypes.byref(fn), ws, need, None, None) == -1
+    assert L.ms_keys(ki, fake(0x1000000 + 8), None, n, 32, ctypes.byref(fn), ws, need, None,
+                     None) == -1
+    # n >= 2^32 - 1
+    assert L.ms_keys(ki, ko, None, 2**32, 32, ctypes.byref(fn), ws, need, None, None) == -1
+    # bucket function that can reach m or beyond
+    bad = BucketFnC(0, 27, 63, 0, None, None)
+    assert L.ms_keys(ki, ko, None, n, 32, ctypes.byref(bad), ws, need, None, None) == -4
+    bad = BucketFnC(1, 0, 0, 1000, None, None)
+    assert L.ms_keys(ki, ko, None, n, 32, ctypes.byref(bad), ws, need, None, None) == -4
+    bad = BucketFnC(2, 0, 0, 0, None, None)
+    assert L.ms_keys(ki, ko, None, n, 32, ctypes.byref(bad), ws, need, None, None) == -1
+    bad = BucketFnC(7, 0, 0, 0, None, None)
+    assert L.ms_keys(ki, ko, None, n, 32, ctypes.byref(bad), ws, need, None, None) == -1
+    # workspace too small or missing
+    assert L.ms_keys(ki, ko, None, n, 32, ctypes.byref(fn), ws, need - 1, None, None) == -2
+    assert L.ms_keys(ki, ko, None, n, 32, ctypes.byref(fn), None, need, None, None) == -2
+    # unsupported shape and bad options
+    o = OptionsC(1, 6, 8, 0, None, None)
+    assert L.ms_keys(ki, ko, None, n, 32, ctypes.byref(fn), ws, need, ctypes.byref(o), None) == -6
+    o = OptionsC(9, 0, 0, 0, None, None)
+    assert L.ms_keys(ki, ko, None, n, 32, ctypes.byref(fn), ws, need, ctypes.byref(o), None) == -1
+    # pairs: values missing on one side
+    assert L.ms_pairs(ki, None, ko, fake(0x30000000), None, n, 32, ctypes.byref(fn), ws, need,
+                      None, None) == -1
+    # radix sort: bits per pass out of range
+    assert L.ms_radix_sort(ki, None, ko, None, n, 9, ws, 1 << 30, None, None) == -1
+    assert L.ms_radix_sort(ki, None, ko, None, n, 0, ws, 1 << 30, None, None) == -1
+
+
+def test_workspace_sizes(L):
+    from paper_1701_01189_amd.binding import OptionsC
+    a = L.ms_workspace_size(0, 1 << 20, 8, 0, None)
+    b = L.ms_workspace_size(0, 1 << 28, 256, 0, None)
+    assert 0 < a < b
+    assert b < 8 << 20  # H stays small: m x L0 words
+    r = L.ms_workspace_size(4, 1 << 28, 256, 0, None)
+    assert r >= 2 * 4 * (1 << 28)  # ping-pong keys and values
+    assert L.ms_workspace_size(0, 1000, 0, 0, None) == 0
+    o = OptionsC(2, 8, 8, 0, None, None)
+    assert L.ms_workspace_size(1, 1 << 25, 32, 0, ctypes.byref(o)) > 0
