@@ -24,8 +24,9 @@
 //   * batched multisplit -- the stable multisplit applied to each segment on
 //     its own; offsets are relative to the segment start.
 //   * learned bucket identifier -- a two-stage piecewise-linear model of the
-//     bucket as a function of the key, fit by least squares in double
-//     precision, evaluated in single precision with fused multiply-add.  It is
+//     bucket as a function of the key (an even split of the key range into
+//     leaves, then a least-squares line per leaf) fit in double precision,
+//     evaluated in single precision with fused multiply-add.  It is
 //     not in the paper (the paper's range buckets use binary search); its
 //     corrected output must equal the upper bound exactly, which is how it is
 //     pinned.  Only the fitted parameter bits are checked to a tolerance.
@@ -151,7 +152,7 @@ int or_batched(const uint32_t* keys, const uint32_t* vals, const uint64_t* seg,
 //   x    = (float)k                       (round to nearest even)
 //   v    = fmaf(a0, x, b0);   leaf = v < 0 ? 0 : v >= L ? L-1 : trunc(v)
 //   w    = fmaf(a_leaf, x, b_leaf); pred = w < 0 ? 0 : w >= m ? m-1 : trunc(w)
-// The root is fit to the target y * L / m so that its output indexes leaves.
+// The root spreads the sample's key range evenly over the leaves.
 // ---------------------------------------------------------------------------
 static const uint32_t OR_LEAVES = 256;
 
@@ -194,22 +195,29 @@ static void lsq_line(const std::vector<double>& x, const std::vector<double>& y,
 }
 
 // Fit the two-stage model to sample keys labelled by the exact upper bound.
-// Steps: label; root least squares of y*L/m on x; route every sample by the
-// float root; least squares of y on x per leaf; an empty leaf copies the
-// nearest non-empty leaf to its left (else to its right).
+// Root: the line that maps the sample's key range [x_min, x_max] onto the
+// leaves [0, L) (x_min to 0, x_max to L, clamped to L-1), so that every leaf
+// covers an equal slice of the key range.  Leaves: least squares of the
+// bucket centre y + 1/2 on x over the samples the float root routes there,
+// so truncation of the line lands inside the bucket.  An empty leaf copies
+// the nearest non-empty leaf to its left (else to its right).
 void or_learned_fit(const uint32_t* sample, uint64_t ns, const uint32_t* spl,
                     uint32_t m, float* model) {
-  std::vector<double> x(ns), y(ns), t(ns);
+  std::vector<double> x(ns), y(ns);
+  double xmin = 0, xmax = 0;
   for (uint64_t i = 0; i < ns; ++i) {
     x[i] = (double)(float)sample[i];
-    y[i] = (double)upper_bound_count(spl, m - 1, sample[i]);
-    t[i] = y[i] * (double)OR_LEAVES / (double)m;
+    y[i] = (double)upper_bound_count(spl, m - 1, sample[i]) + 0.5;
+    if (i == 0 || x[i] < xmin) xmin = x[i];
+    if (i == 0 || x[i] > xmax) xmax = x[i];
   }
-  double a0, b0;
-  int ok;
-  lsq_line(x, t, &a0, &b0, &ok);
-  model[0] = (float)a0;
-  model[1] = (float)b0;
+  float a0 = 0.0f, b0 = 0.0f;
+  if (xmax > xmin) {
+    a0 = (float)((double)OR_LEAVES / (xmax - xmin));
+    b0 = (float)(-(double)a0 * xmin);
+  }
+  model[0] = a0;
+  model[1] = b0;
   std::vector<std::vector<double>> lx(OR_LEAVES), ly(OR_LEAVES);
   for (uint64_t i = 0; i < ns; ++i) {
     uint32_t l = or_learned_leaf(model, sample[i]);

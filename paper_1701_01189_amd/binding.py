@@ -242,6 +242,22 @@ def radix_sort(keys_in, vals_in=None, bits_per_pass=8, keys_out=None, vals_out=N
     return keys_out, vals_out
 
 
+def learned_fit(sample, splitters, m, model=None, stream=None, ws=None):
+    """Fits the two-stage learned bucket model on the GPU.  Returns the model
+    tensor (MODEL_FLOATS float32)."""
+    import torch
+    if model is None:
+        model = torch.empty(MODEL_FLOATS, dtype=torch.float32, device=sample.device)
+    n = sample.numel()
+    if ws is None:
+        need = workspace_size(OP_LEARNED_FIT, n, m)
+        ws = torch.empty(max(need, 256), dtype=torch.uint8, device=sample.device)
+    rc = lib().ms_learned_fit(_u32(sample, "sample"), n, _u32(splitters, "splitters"), m,
+                              _ptr(model), _ptr(ws), ws.numel(), _stream(stream))
+    _check(rc, "ms_learned_fit")
+    return model
+
+
 def copy_u32(dst, src, stream=None):
     rc = lib().ms_copy_u32(_u32(dst, "dst"), _u32(src, "src"), src.numel(), _stream(stream))
     _check(rc, "ms_copy_u32")

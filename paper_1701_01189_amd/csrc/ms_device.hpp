@@ -43,23 +43,35 @@ __device__ __forceinline__ uint32_t popc64(uint64_t x) {
   return (uint32_t)__builtin_popcountll(x);
 }
 
-// ~(b ^ sel): b where sel is all ones, ~b where sel is zero.
-__device__ __forceinline__ uint64_t pick(uint64_t b, uint64_t sel) { return ~(b ^ sel); }
+// m & ~(b ^ sel) in one gfx950 three-input bitwise op: keeps the bits of m
+// where the ballot b agrees with the selector (sel all ones: b; zero: ~b).
+// Truth table over (S0, S1, S2) = (0xF0, 0xCC, 0xAA): 0xF0 & ~(0xCC ^ 0xAA).
+__device__ __forceinline__ uint32_t and_agree(uint32_t m, uint32_t b, uint32_t sel) {
+  return __builtin_amdgcn_bitop3_b32(m, b, sel, 0x90);
+}
 
-// Lanes whose (valid) element has the same bucket as this lane's element.
-// Section 5.4: the vote of every lane is published one bit at a time with
-// BITS = ceil(log2 m) ballots; Algorithm 3 keeps, per lane, the lanes whose
-// vote agrees with its own vote on every bit.
+// Bit k of b spread over a word: 0 or 0xFFFFFFFF (a signed bit-field extract).
+__device__ __forceinline__ uint32_t bit_spread(uint32_t b, int k) {
+  return (uint32_t)(((int32_t)(b << (31 - k))) >> 31);
+}
+
+// Lanes whose element has the same bucket as this lane's element, among the
+// lanes of valid_mask.  Section 5.4: every lane publishes its vote one bit
+// at a time with BITS = ceil(log2 m) ballots; Algorithm 3 keeps, per lane,
+// the lanes that agree with its own vote on every bit.  Invalid lanes must
+// carry bucket 0 (they then vote 0 on every bit and are removed by
+// valid_mask).
 template <int BITS>
-__device__ __forceinline__ uint64_t match_bucket(uint32_t b, bool valid, uint64_t valid_mask) {
-  uint64_t m = valid_mask;
+__device__ __forceinline__ uint64_t match_bucket(uint32_t b, uint64_t valid_mask) {
+  uint32_t lo = (uint32_t)valid_mask, hi = (uint32_t)(valid_mask >> 32);
 #pragma unroll
   for (int k = 0; k < BITS; ++k) {
-    uint32_t bit = (b >> k) & 1u;
-    uint64_t bal = ballot(valid && bit);
-    m &= pick(bal, (uint64_t)0 - (uint64_t)bit);
+    const uint32_t sel = bit_spread(b, k);
+    const uint64_t bal = ballot(sel != 0u);
+    lo = and_agree(lo, (uint32_t)bal, sel);
+    hi = and_agree(hi, (uint32_t)(bal >> 32), sel);
   }
-  return m;
+  return ((uint64_t)hi << 32) | lo;
 }
 
 // Buckets owned per lane by the histogram solve: ceil(2^BITS / 64).
@@ -68,31 +80,55 @@ struct Owned {
   static constexpr int value = BITS <= 6 ? 1 : (1 << (BITS - 6));
 };
 
+// Per-lane selectors of Algorithm 2: bit k of the lane index, spread.
+struct LaneSel {
+  uint32_t s[6];
+  __device__ explicit LaneSel(uint32_t lane) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) s[k] = bit_spread(lane, k);
+  }
+};
+
 // Algorithm 2 generalised to wave64 and m <= 256 (Section 5.7): lane l owns
 // buckets l + 64 t, t < ceil(m/64).  For vote bits k < 6 the lane compares
 // the ballot with its own lane bit (lane-dependent); for k >= 6 the owned
 // bucket's bit is bit (k-6) of t, the same for all lanes, so that part of the
 // mask is a uniform (scalar) value per t.  cnt[t] += count of bucket l+64t.
+// Invalid lanes must carry bucket 0.
 template <int BITS>
-__device__ __forceinline__ void window_histogram(uint32_t b, bool valid, uint64_t valid_mask,
-                                                 uint32_t lane,
+__device__ __forceinline__ void window_histogram(uint32_t b, uint64_t valid_mask,
+                                                 const LaneSel& ls,
                                                  uint32_t (&cnt)[Owned<BITS>::value]) {
   constexpr int MB = Owned<BITS>::value;
   uint64_t bal[BITS > 0 ? BITS : 1];
 #pragma unroll
-  for (int k = 0; k < BITS; ++k) bal[k] = ballot(valid && ((b >> k) & 1u));
-  uint64_t low = valid_mask;
+  for (int k = 0; k < BITS; ++k) bal[k] = ballot(bit_spread(b, k) != 0u);
+  uint32_t lo = (uint32_t)valid_mask, hi = (uint32_t)(valid_mask >> 32);
 #pragma unroll
-  for (int k = 0; k < (BITS < 6 ? BITS : 6); ++k)
-    low &= pick(bal[k], (uint64_t)0 - (uint64_t)((lane >> k) & 1u));
+  for (int k = 0; k < (BITS < 6 ? BITS : 6); ++k) {
+    lo = and_agree(lo, (uint32_t)bal[k], ls.s[k]);
+    hi = and_agree(hi, (uint32_t)(bal[k] >> 32), ls.s[k]);
+  }
 #pragma unroll
   for (int t = 0; t < MB; ++t) {
     uint64_t s = ~0ull;
 #pragma unroll
     for (int k = 6; k < BITS; ++k) s &= ((t >> (k - 6)) & 1) ? bal[k] : ~bal[k];
-    cnt[t] += popc64(low & s);
+    cnt[t] += __builtin_popcount(lo & (uint32_t)s) + __builtin_popcount(hi & (uint32_t)(s >> 32));
   }
 }
+
+// LDS words shared by the lanes of one wavefront between ballot windows.
+// Relaxed wavefront-scope atomics compile to plain ds_read/ds_write (a
+// wavefront's LDS operations complete in order) while keeping the compiler
+// from caching or forwarding values that another lane wrote.
+__device__ __forceinline__ uint32_t lds_get(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+__device__ __forceinline__ void lds_put(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+__device__ __forceinline__ void wave_order() { __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront"); }
 
 // ---------------------------------------------------------------------------
 // scans
@@ -124,10 +160,13 @@ struct BucketParams {
   unsigned long long* mispredicts;
 };
 
-// Range-bucket lookup tables staged in LDS: splitters padded to a power of
-// two with 0xFFFFFFFF, and the learned model.
+// Range-bucket lookup tables staged in LDS.  spl[] holds two zero words
+// (splitter indices -2 and -1: every key is >= them), the m-1 splitters from
+// index 2 on, then 0xFFFFFFFF padding up to a power of two; model[] is the
+// learned model (2 root floats, then slope and intercept of each leaf).
+constexpr int kSplPad = 2;
 struct BucketLds {
-  uint32_t spl[kMaxBuckets];
+  uint32_t spl[kSplPad + kMaxBuckets + 2];
   float model[kModelFloats];
 };
 
@@ -175,48 +214,50 @@ template <int BITS>
 struct Bucket<kSplitters, BITS> {
   const uint32_t* spl;
   uint32_t m;
-  __device__ Bucket(const BucketParams& p, const BucketLds* l) : spl(l->spl), m(p.m) {}
+  __device__ Bucket(const BucketParams& p, const BucketLds* l) : spl(l->spl + kSplPad), m(p.m) {}
   __device__ __forceinline__ uint32_t operator()(uint32_t k) const {
     return lds_upper_bound<BITS>(spl, m, k);
   }
   __device__ __forceinline__ uint32_t misses() const { return 0; }
 };
 
-// Learned identifier: x = (float)k; leaf = clamp(trunc(fma(a0, x, b0)));
-// guess = clamp(trunc(fma(a_leaf, x, b_leaf)), 0, m-1); then an exact check
-// s[guess-1] <= k < s[guess] (open ends at 0 and m-1), one step down or up,
-// else the binary search.  The returned id always equals the upper bound.
+// Learned identifier (not in the paper; binary search is the paper's way):
+//   x = (float)k;  leaf = trunc(clamp(fma(a0, x, b0), 0, 255));
+//   g = trunc(clamp(fma(a_leaf, x, b_leaf), 0, m-1))
+// then one branch-free step: down if k < s[g-1], up if k >= s[g] (s[-1] =
+// -inf, s[m-1] = +inf).  The stepped bucket is checked against its other
+// neighbouring splitter; only if that fails (the model was off by more than
+// one bucket) does the lane fall back to the binary search.  The result is
+// always the upper bound.  clamp-then-truncate equals the oracle's
+// "< 0 -> 0, >= hi -> hi-1, else truncate" for finite values.
 __device__ __forceinline__ uint32_t clamp_trunc(float v, uint32_t hi) {
-  if (v < 0.0f) return 0;
-  if (v >= (float)hi) return hi - 1;
-  return (uint32_t)v;
+  return (uint32_t)__builtin_amdgcn_fmed3f(v, 0.0f, (float)(hi - 1));
 }
 
 template <int BITS>
 struct Bucket<kLearned, BITS> {
-  const uint32_t* spl;
+  const uint32_t* tbl;  // spl with the two zero words in front
   const float* model;
   uint32_t m;
   mutable uint32_t miss;
   __device__ Bucket(const BucketParams& p, const BucketLds* l)
-      : spl(l->spl), model(l->model), m(p.m), miss(0) {}
-  __device__ __forceinline__ bool in_bucket(uint32_t g, uint32_t k) const {
-    bool lo = (g == 0) || (spl[g - 1] <= k);
-    bool hi = (g + 1 >= m) || (k < spl[g]);
-    return lo && hi;
-  }
+      : tbl(l->spl), model(l->model), m(p.m), miss(0) {}
   __device__ __forceinline__ uint32_t predict(uint32_t k) const {
-    float x = (float)k;
-    uint32_t leaf = clamp_trunc(__builtin_fmaf(model[0], x, model[1]), (uint32_t)kLeaves);
-    return clamp_trunc(__builtin_fmaf(model[2 + 2 * leaf], x, model[3 + 2 * leaf]), m);
+    const float x = (float)k;
+    const uint32_t leaf = clamp_trunc(__builtin_fmaf(model[0], x, model[1]), (uint32_t)kLeaves);
+    const float2 ab = reinterpret_cast<const float2*>(model + 2)[leaf];
+    return clamp_trunc(__builtin_fmaf(ab.x, x, ab.y), m);
   }
   __device__ __forceinline__ uint32_t operator()(uint32_t k) const {
-    uint32_t g = predict(k);
-    if (in_bucket(g, k)) return g;
-    miss += 1;
-    if (g > 0 && in_bucket(g - 1, k)) return g - 1;
-    if (g + 1 < m && in_bucket(g + 1, k)) return g + 1;
-    return lds_upper_bound<BITS>(spl, m, k);
+    const uint32_t g = predict(k);
+    const uint32_t sm2 = tbl[g], sm1 = tbl[g + 1], s0 = tbl[g + 2], sp1 = tbl[g + 3];
+    const bool down = k < sm1;                 // s[g-1] > k
+    const bool up = (g + 1 < m) && k >= s0;    // s[g] <= k
+    uint32_t c = g - (down ? 1u : 0u) + (up ? 1u : 0u);
+    const bool bad = (down && k < sm2) || (up && g + 2 < m && k >= sp1);
+    if (bad) c = lds_upper_bound<BITS>(tbl + kSplPad, m, k);
+    miss += (c != g) ? 1u : 0u;
+    return c;
   }
   __device__ __forceinline__ uint32_t misses() const { return miss; }
 };
@@ -225,8 +266,12 @@ struct Bucket<kLearned, BITS> {
 template <int Kind>
 __device__ __forceinline__ void stage_bucket_tables(const BucketParams& p, BucketLds* l) {
   if (Kind == kSplitters || Kind == kLearned) {
-    for (uint32_t i = threadIdx.x; i < (uint32_t)kMaxBuckets; i += blockDim.x)
-      l->spl[i] = (i + 1 < p.m) ? p.splitters[i] : 0xFFFFFFFFu;
+    for (uint32_t i = threadIdx.x; i < (uint32_t)(kSplPad + kMaxBuckets + 2); i += blockDim.x) {
+      uint32_t v;
+      if (i < (uint32_t)kSplPad) v = 0u;
+      else v = (i - kSplPad + 1 < p.m) ? p.splitters[i - kSplPad] : 0xFFFFFFFFu;
+      l->spl[i] = v;
+    }
   }
   if (Kind == kLearned) {
     for (uint32_t i = threadIdx.x; i < (uint32_t)kModelFloats; i += blockDim.x)

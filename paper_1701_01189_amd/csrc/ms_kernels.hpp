@@ -9,6 +9,8 @@
 // wavefront for WMS/DMS, a workgroup for BMS) -- one column of H.
 #pragma once
 
+#include <type_traits>
+
 #include "ms_device.hpp"
 
 namespace ms {
@@ -31,8 +33,8 @@ __device__ __forceinline__ void group_sync() {
   if (WPG > 1) {
     __syncthreads();
   } else {
-    // one wavefront: LDS operations of a wavefront complete in order; only
-    // the compiler has to be kept from moving accesses across this point.
+    // one wavefront: its LDS operations complete in order; only the
+    // compiler has to be kept from moving accesses across this point.
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -85,6 +87,7 @@ prescan_kernel(const uint32_t* __restrict__ keys, Plan plan, BucketParams bp,
   Bucket<Kind, BITS> bf(bp, &tables);
 
   const uint32_t lane = lane_id();
+  const LaneSel ls(lane);
   const uint32_t w = threadIdx.x / kWave;
   const uint32_t g = w / WPG, wg = w % WPG;
   const uint32_t c = (GPB == 1 ? xcd_chunk(blockIdx.x, gridDim.x) : blockIdx.x * GPB + g);
@@ -95,27 +98,43 @@ prescan_kernel(const uint32_t* __restrict__ keys, Plan plan, BucketParams bp,
   if (c < plan.L0) {
     const uint32_t c0 = c * plan.chunk;
     const uint32_t len = min(plan.chunk, plan.n - c0);
-    const uint32_t groups = (uint32_t)(((uint64_t)len + U * kWave - 1) / (U * kWave));
-    for (uint32_t gi = wg; gi < groups; gi += WPG) {
-      const uint32_t base = c0 + gi * (U * kWave);
-      const uint32_t rem = len - gi * (U * kWave);
-      if (rem >= (uint32_t)(U * kWave)) {
-        uint32_t k[U];
+    constexpr uint32_t BATCH = U * kWave;
+    const uint32_t full = len / BATCH;       // complete batches of U windows
+    const uint32_t* base = keys + c0 + lane;
+    // Complete batches, software pipelined: the bucket ids of a batch are
+    // computed first (their table lookups overlap), then the next batch's
+    // loads are issued into the freed registers while the histogram solve
+    // of this batch runs.
+    uint32_t gi = wg;
+    uint32_t k[U];
+    if (gi < full) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) k[u] = keys[base + u * kWave + lane];
+      for (int u = 0; u < U; ++u) k[u] = base[gi * BATCH + u * kWave];
+    }
+    while (gi < full) {
+      uint32_t b[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          window_histogram<BITS>(bf(k[u]), true, ~0ull, lane, cnt);
-          __builtin_amdgcn_sched_barrier(0);
-        }
-      } else {
-        for (int u = 0; u < U; ++u) {
-          const uint32_t off = u * kWave + lane;
-          const bool valid = off < rem;
-          uint32_t kk = valid ? keys[base + off] : 0u;
-          uint32_t b = valid ? bf(kk) : 0u;
-          window_histogram<BITS>(b, valid, ballot(valid), lane, cnt);
-        }
+      for (int u = 0; u < U; ++u) b[u] = bf(k[u]);
+      const uint32_t next = gi + WPG;
+      if (next < full) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) k[u] = base[next * BATCH + u * kWave];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        window_histogram<BITS>(b[u], ~0ull, ls, cnt);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      gi = next;
+    }
+    // The incomplete last batch, if any, belongs to one wavefront.
+    const uint32_t rem = len - full * BATCH;
+    if (rem > 0 && wg == full % WPG) {
+      const uint32_t* p = base + full * BATCH;
+      for (int u = 0; u < U; ++u) {
+        const bool valid = (uint32_t)(u * kWave) + lane < rem;
+        const uint32_t b = valid ? bf(p[u * kWave]) : 0u;
+        window_histogram<BITS>(b, ballot(valid), ls, cnt);
       }
     }
   }
@@ -221,35 +240,37 @@ postscan_kernel(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict
   if (c >= plan.L0) return;  // only whole idle groups leave (never a BMS group)
   const uint32_t c0 = c * plan.chunk;
   const uint32_t len = min(plan.chunk, plan.n - c0);
-  volatile uint32_t* my_cnt = s_cnt + w * CNT_STRIDE;
+  uint32_t* my_cnt = s_cnt + w * CNT_STRIDE;
   uint32_t* run = s_run + g * kMaxBuckets;
 
   if (MODE == kDirect) {
     // DMS: counters are the running output positions of this wavefront.
-    for (uint32_t b = lane; b < m; b += kWave) my_cnt[b] = run[b];
-    group_sync<1>();
+    for (uint32_t b = lane; b < m; b += kWave) lds_put(my_cnt + b, run[b]);
+    wave_order();
     const uint32_t steps = (uint32_t)(((uint64_t)len + NW * kWave - 1) / (NW * kWave));
     for (uint32_t si = 0; si < steps; ++si) {
-      const uint32_t base = c0 + si * (NW * kWave);
       const uint32_t rem = len - si * (NW * kWave);
+      // invalid lanes read the step's first element, which always exists
+      const uint32_t* bk0 = keys_in + c0 + si * (NW * kWave);
+      const uint32_t* bv0 = vals_in + c0 + si * (NW * kWave);
       uint32_t k[NW], v[NW];
 #pragma unroll
       for (int j = 0; j < NW; ++j) {
-        const uint32_t off = j * kWave + lane;
-        const bool valid = off < rem;
-        k[j] = valid ? keys_in[base + off] : 0u;
-        if (KV) v[j] = valid ? vals_in[base + off] : 0u;
+        const bool valid = (uint32_t)(j * kWave) + lane < rem;
+        const uint32_t o = valid ? (uint32_t)(j * kWave) + lane : 0u;
+        k[j] = bk0[o];
+        if (KV) v[j] = bv0[o];
       }
 #pragma unroll
       for (int j = 0; j < NW; ++j) {
         const bool valid = (uint32_t)(j * kWave) + lane < rem;
-        uint32_t b = valid ? bf(k[j]) : 0u;
-        uint64_t vm = ballot(valid);
-        uint64_t mm = match_bucket<BITS>(b, valid, vm);
-        uint32_t r = count_below(mm), cnt = popc64(mm);
-        uint32_t pos = my_cnt[b];
-        if (valid && r + 1 == cnt) my_cnt[b] = pos + cnt;
-        uint32_t o = pos + r;
+        const uint32_t b = valid ? bf(k[j]) : 0u;
+        const uint64_t mm = match_bucket<BITS>(b, ballot(valid));
+        const uint32_t r = count_below(mm), cnt = popc64(mm);
+        const uint32_t pos = lds_get(my_cnt + b);
+        if (valid && r + 1 == cnt) lds_put(my_cnt + b, pos + cnt);
+        wave_order();
+        const uint32_t o = pos + r;
         if (valid && o < plan.n) {
           keys_out[o] = k[j];
           if (KV) vals_out[o] = v[j];
@@ -261,44 +282,75 @@ postscan_kernel(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict
     uint32_t* s_v = s_vals + (KV ? g * T : 0);
     uint8_t* s_b = s_bk + g * T;
     uint32_t* delta = s_delta + g * kMaxBuckets;
-    volatile uint32_t* grp_cnt = s_cnt + (g * WPG) * CNT_STRIDE;
+    uint32_t* grp_cnt = s_cnt + (g * WPG) * CNT_STRIDE;
     const uint32_t ntiles = (uint32_t)(((uint64_t)len + T - 1) / T);
-    for (uint32_t ti = 0; ti < ntiles; ++ti) {
+    const uint32_t wbase = wg * NW * kWave;
+    uint32_t k[NW], v[NW];
+
+    // Loads of tile ti into k, v (element (wg, j, lane) of the tile).  In a
+    // partial tile, lanes past the end read the tile's first element, which
+    // always exists, and are masked out later.
+    auto load = [&](uint32_t ti, auto full_tag) {
+      constexpr bool FULL = decltype(full_tag)::value;
       const uint32_t tb = c0 + ti * T;
-      const uint32_t tcount = min((uint32_t)T, len - ti * T);
-      for (uint32_t b = lane; b < m; b += kWave) my_cnt[b] = 0u;
-      uint32_t k[NW], v[NW], bk[NW], lr[NW];
+      const uint32_t tcount = FULL ? (uint32_t)T : min((uint32_t)T, len - ti * T);
+      const uint32_t* pk = keys_in + tb + wbase + lane;
+      const uint32_t* pv = vals_in + tb + wbase + lane;
 #pragma unroll
       for (int j = 0; j < NW; ++j) {
-        const uint32_t off = (wg * NW + j) * kWave + lane;
-        const bool valid = off < tcount;
-        k[j] = valid ? __builtin_nontemporal_load(keys_in + tb + off) : 0u;
-        if (KV) v[j] = valid ? __builtin_nontemporal_load(vals_in + tb + off) : 0u;
+        if (FULL) {
+          k[j] = __builtin_nontemporal_load(pk + j * kWave);
+          if (KV) v[j] = __builtin_nontemporal_load(pv + j * kWave);
+        } else {
+          const bool valid = wbase + (uint32_t)(j * kWave) + lane < tcount;
+          k[j] = __builtin_nontemporal_load(valid ? pk + j * kWave : keys_in + tb);
+          if (KV) v[j] = __builtin_nontemporal_load(valid ? pv + j * kWave : vals_in + tb);
+        }
       }
-      group_sync<1>();
+    };
+    auto load_tile = [&](uint32_t ti) {
+      if (len - ti * T >= (uint32_t)T)
+        load(ti, std::true_type{});
+      else
+        load(ti, std::false_type{});
+    };
+
+    // One tile whose keys (and values) are already in k, v.  The loads of
+    // the next tile are issued once k, v have been written to LDS, so they
+    // overlap the write-back of this tile.
+    auto tile = [&](uint32_t ti, auto full_tag) {
+      constexpr bool FULL = decltype(full_tag)::value;
+      const uint32_t tcount = FULL ? (uint32_t)T : min((uint32_t)T, len - ti * T);
+      for (uint32_t b = lane; b < m; b += kWave) lds_put(my_cnt + b, 0u);
+      uint32_t bk[NW], lr[NW];
+#pragma unroll
+      for (int j = 0; j < NW; ++j) {
+        const bool valid = FULL || wbase + (uint32_t)(j * kWave) + lane < tcount;
+        bk[j] = valid ? bf(k[j]) : 0u;
+      }
+      wave_order();
       // ranking: Algorithm 3 per window + per-wavefront running counts
 #pragma unroll
       for (int j = 0; j < NW; ++j) {
-        const bool valid = (wg * NW + j) * kWave + lane < tcount;
-        bk[j] = valid ? bf(k[j]) : 0u;
-        uint64_t vm = ballot(valid);
-        uint64_t mm = match_bucket<BITS>(bk[j], valid, vm);
-        uint32_t r = count_below(mm), cnt = popc64(mm);
-        uint32_t before = my_cnt[bk[j]];
+        const bool valid = FULL || wbase + (uint32_t)(j * kWave) + lane < tcount;
+        const uint64_t mm = match_bucket<BITS>(bk[j], FULL ? ~0ull : ballot(valid));
+        const uint32_t r = count_below(mm), cnt = popc64(mm);
+        const uint32_t before = lds_get(my_cnt + bk[j]);
         lr[j] = before + r;
-        if (valid && r + 1 == cnt) my_cnt[bk[j]] = before + cnt;
+        if (valid && r + 1 == cnt) lds_put(my_cnt + bk[j], before + cnt);
+        wave_order();
       }
       group_sync<WPG>();
       // exclusive scan of the bucket-major table: entry e = b*WPG + wave
       {
         const uint32_t E = m * WPG;
         const uint32_t ept = (E + WPG * kWave - 1) / (WPG * kWave);
-        uint32_t e0 = tid_g * ept;
+        const uint32_t e0 = tid_g * ept;
         uint32_t vals[4];
         uint32_t s = 0;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          uint32_t e = e0 + i;
+          const uint32_t e = e0 + i;
           vals[i] = ((uint32_t)i < ept && e < E) ? grp_cnt[(e % WPG) * CNT_STRIDE + e / WPG] : 0u;
           s += vals[i];
         }
@@ -306,7 +358,7 @@ postscan_kernel(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict
         uint32_t pre = group_exclusive_scan<WPG>(s, s_tmp + g * WPG, wg, lane, &total);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          uint32_t e = e0 + i;
+          const uint32_t e = e0 + i;
           if ((uint32_t)i < ept && e < E) grp_cnt[(e % WPG) * CNT_STRIDE + e / WPG] = pre;
           pre += vals[i];
         }
@@ -314,30 +366,32 @@ postscan_kernel(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict
       group_sync<WPG>();
       // tile bucket starts -> output delta; advance the running bases
       for (uint32_t b = tid_g; b < m; b += WPG * kWave) {
-        uint32_t st = grp_cnt[b];
-        uint32_t nx = (b + 1 < m) ? grp_cnt[b + 1] : tcount;
+        const uint32_t st = grp_cnt[b];
+        const uint32_t nx = (b + 1 < m) ? grp_cnt[b + 1] : tcount;
         delta[b] = run[b] - st;
         run[b] += nx - st;
       }
       // local reorder: slot = tile base of (bucket, wavefront) + rank
 #pragma unroll
       for (int j = 0; j < NW; ++j) {
-        if ((wg * NW + j) * kWave + lane < tcount) {
-          uint32_t slot = my_cnt[bk[j]] + lr[j];
+        const bool valid = FULL || wbase + (uint32_t)(j * kWave) + lane < tcount;
+        if (valid) {
+          const uint32_t slot = my_cnt[bk[j]] + lr[j];
           s_k[slot] = k[j];
           if (KV) s_v[slot] = v[j];
           s_b[slot] = (uint8_t)bk[j];
         }
       }
       group_sync<WPG>();
+      if (ti + 1 < ntiles) load_tile(ti + 1);
       // coalesced write-back: consecutive slots of a bucket are consecutive
       // output positions
 #pragma unroll
       for (int j = 0; j < NW; ++j) {
-        uint32_t q = j * (WPG * kWave) + tid_g;
-        if (q < tcount) {
-          uint32_t b = s_b[q];
-          uint32_t o = delta[b] + q;
+        const uint32_t q = j * (WPG * kWave) + tid_g;
+        if (FULL || q < tcount) {
+          const uint32_t b = s_b[q];
+          const uint32_t o = delta[b] + q;
           if (o < plan.n) {
             keys_out[o] = s_k[q];
             if (KV) vals_out[o] = s_v[q];
@@ -345,6 +399,14 @@ postscan_kernel(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict
         }
       }
       group_sync<WPG>();
+    };
+
+    if (ntiles > 0) load_tile(0);
+    for (uint32_t ti = 0; ti < ntiles; ++ti) {
+      if (len - ti * T >= (uint32_t)T)
+        tile(ti, std::true_type{});
+      else
+        tile(ti, std::false_type{});
     }
   }
   if (Kind == kLearned && bp.mispredicts) {

@@ -11,6 +11,7 @@
 
 #include "../../include/multisplit.h"
 #include "ms_aux_kernels.hpp"
+#include "ms_learned.hpp"
 #include "ms_dispatch.hpp"
 
 namespace {
@@ -286,6 +287,11 @@ size_t ms_workspace_size(int op, size_t n, uint32_t m, uint32_t num_inst, const 
       size_t data = align_up(n * 4, kWsAlign) * (kv ? 2 : 1);
       return data + ms_ws_bytes(make_plan(n, 256, s, kv));
     }
+    case MS_OP_LEARNED_FIT: {
+      if (n == 0 || n >= 0xFFFFFFFFull) return 0;
+      return align_up(2 * ms::kFitBlocks * sizeof(double), kWsAlign) +
+             align_up((8 + ms::kLeaves) * sizeof(double), kWsAlign) + 2 * align_up(n * 4, kWsAlign);
+    }
     default:
       return 0;
   }
@@ -383,9 +389,33 @@ ms_status ms_batched(const uint32_t* d_keys_in, const uint32_t* d_vals_in, uint3
 
 ms_status ms_learned_fit(const uint32_t* d_sample, size_t n_sample, const uint32_t* d_splitters,
                          uint32_t m, float* d_model, void* d_ws, size_t ws_bytes, void* stream) {
-  (void)d_sample; (void)n_sample; (void)d_splitters; (void)m; (void)d_model; (void)d_ws;
-  (void)ws_bytes; (void)stream;
-  return MS_ERR_UNSUPPORTED;
+  if (m < 1 || m > (uint32_t)ms::kMaxBuckets) return MS_ERR_INVALID_ARG;
+  if (n_sample == 0 || n_sample >= 0xFFFFFFFFull) return MS_ERR_INVALID_ARG;
+  if (!d_sample || !d_model || (m > 1 && !d_splitters)) return MS_ERR_INVALID_ARG;
+  size_t need = ms_workspace_size(MS_OP_LEARNED_FIT, n_sample, m, 0, nullptr);
+  if (!d_ws || ws_bytes < need) return MS_ERR_WORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  char* b = (char*)d_ws;
+  ms::FitParams p;
+  p.sample = d_sample;
+  p.ns = (uint32_t)n_sample;
+  p.splitters = d_splitters;
+  p.m = m;
+  p.model = d_model;
+  p.partial = (double*)b;
+  b += align_up(2 * ms::kFitBlocks * sizeof(double), kWsAlign);
+  p.moments = (double*)b;
+  b += align_up((8 + ms::kLeaves) * sizeof(double), kWsAlign);
+  p.labels = (uint32_t*)b;
+  b += align_up(n_sample * 4, kWsAlign);
+  p.leaves = (uint32_t*)b;
+  dim3 G(ms::kFitBlocks), B(ms::kFitThreads);
+  hipLaunchKernelGGL(ms::fit_label_kernel, G, B, 0, st, p);
+  hipLaunchKernelGGL(ms::fit_root_kernel, dim3(1), B, 0, st, p);
+  hipLaunchKernelGGL(ms::fit_route_kernel, G, B, 0, st, p);
+  hipLaunchKernelGGL(ms::fit_leaf_kernel, dim3(ms::kLeaves), B, 0, st, p);
+  hipLaunchKernelGGL(ms::fit_fill_empty_kernel, dim3(1), dim3(64), 0, st, p);
+  return hipGetLastError() == hipSuccess ? MS_OK : MS_ERR_HIP;
 }
 
 ms_status ms_copy_u32(uint32_t* d_dst, const uint32_t* d_src, size_t n, void* stream) {

@@ -1,0 +1,136 @@
+"""GPU parity of range buckets: binary search over splitters and the learned
+bucket identifier (model prediction + exact correction) against the oracle.
+
+The learned path must give exactly the upper-bound bucket of every key, so
+its multisplit output is compared bit-exactly with the oracle's splitter
+multisplit.  With the CPU-fitted model loaded, the GPU's count of raw-model
+mispredictions must equal the oracle's count exactly (same float32 fused
+multiply-add evaluation).  The GPU fit itself is compared with the CPU fit
+parameter by parameter (relative 1e-5) and by misprediction rate (within 0.1
+percentage points): the two sum in different orders.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1701_01189_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a).view(np.int32)).cuda()
+
+
+def devf(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def host(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def lognormal_setup(n, fit_n=1 << 18):
+    sample = inputs.lognormal_u32(1031, 1 << 16)
+    spl = inputs.quantile_splitters(sample, 256)
+    fit = inputs.lognormal_u32(1032, fit_n)
+    keys = inputs.lognormal_u32(103, n)
+    return keys, spl, fit
+
+
+SHAPES = [(1, 8, 8), (1, 4, 8), (2, 8, 8), (3, 8, 8)]
+
+
+def test_learned_and_binary_search_match_oracle_with_cpu_model():
+    from paper_1701_01189_amd import binding as ms
+    n = (1 << 22) + 333
+    keys, spl, fit = lognormal_setup(n)
+    model = oracle.learned_fit(fit, spl, 256)
+    ek, _, eo = oracle.multisplit(keys, 256, oracle.SPLITTERS, splitters=spl)
+    _, emiss = oracle.learned_bucket_ids(model, spl, 256, keys)
+    dk, ds, dm = dev(keys), dev(spl), devf(model)
+    for shape in SHAPES:
+        say("case splitters shape=%s" % (shape,))
+        k, o = ms.keys(dk, 256, ms.BucketFn.splitter(ds), options=ms.Options(*shape))
+        np.testing.assert_array_equal(host(k), ek)
+        np.testing.assert_array_equal(host(o), eo)
+        say("case learned shape=%s" % (shape,))
+        miss = torch.zeros(1, dtype=torch.int64, device="cuda")
+        k, o = ms.keys(dk, 256, ms.BucketFn.learned(ds, dm),
+                       options=ms.Options(*shape, mispredicts=miss))
+        np.testing.assert_array_equal(host(k), ek)
+        np.testing.assert_array_equal(host(o), eo)
+        assert int(miss.item()) == emiss
+
+
+def test_learned_pairs_small_m_and_duplicates():
+    from paper_1701_01189_amd import binding as ms
+    for m in (2, 3, 17, 100, 255):
+        n = 50_001 + m
+        keys = inputs.uniform_u32(300 + m, n)
+        vals = inputs.index_values(n)
+        spl = np.sort(inputs.uniform_u32(400 + m, m - 1))
+        if m > 10:
+            spl[3:9] = spl[3]  # zero-width buckets
+            spl = np.sort(spl)
+        keys[:m - 1] = spl   # keys equal to splitters go up
+        model = oracle.learned_fit(inputs.uniform_u32(500 + m, 20_000), spl, m)
+        ek, ev, eo = oracle.multisplit(keys, m, oracle.SPLITTERS, vals=vals, splitters=spl)
+        _, emiss = oracle.learned_bucket_ids(model, spl, m, keys)
+        say("case learned pairs m=%d" % m)
+        miss = torch.zeros(1, dtype=torch.int64, device="cuda")
+        k, v, o = ms.pairs(dev(keys), dev(vals), m, ms.BucketFn.learned(dev(spl), devf(model)),
+                           options=ms.Options(mispredicts=miss))
+        np.testing.assert_array_equal(host(k), ek)
+        np.testing.assert_array_equal(host(v), ev)
+        np.testing.assert_array_equal(host(o), eo)
+        assert int(miss.item()) == emiss
+
+
+def test_gpu_fit_against_cpu_fit():
+    from paper_1701_01189_amd import binding as ms
+    n = 1 << 20
+    keys, spl, fit = lognormal_setup(1 << 20, fit_n=1 << 20)
+    cpu = oracle.learned_fit(fit, spl, 256)
+    say("case gpu fit 2^20")
+    gm = ms.learned_fit(dev(fit), dev(spl), 256)
+    torch.cuda.synchronize()
+    gpu = gm.cpu().numpy()
+    np.testing.assert_allclose(gpu, cpu, rtol=1e-5, atol=1e-12)
+    _, miss_cpu = oracle.learned_bucket_ids(cpu, spl, 256, keys)
+    _, miss_gpu = oracle.learned_bucket_ids(gpu, spl, 256, keys)
+    assert abs(miss_cpu - miss_gpu) / n <= 0.001
+    # deterministic: a second fit is bit-identical
+    gm2 = ms.learned_fit(dev(fit), dev(spl), 256)
+    np.testing.assert_array_equal(gm2.cpu().numpy(), gpu)
+    # and it is a usable model: the multisplit stays exact
+    ek, _, eo = oracle.multisplit(keys, 256, oracle.SPLITTERS, splitters=spl)
+    k, o = ms.keys(dev(keys), 256, ms.BucketFn.learned(dev(spl), gm))
+    np.testing.assert_array_equal(host(k), ek)
+
+
+def test_range_2e27_lognormal_learned_full_size():
+    """n = 2^27 lognormal(20, 2) saturated keys (seed 103), m = 256 buckets at
+    quantiles of a 2^16-key sample (seed 1031); model fit on the GPU from 2^20
+    keys (seed 1032).  Learned and binary-search outputs equal the oracle."""
+    from paper_1701_01189_amd import binding as ms
+    n = 1 << 27
+    keys, spl, fit = lognormal_setup(n, fit_n=1 << 20)
+    ek, _, eo = oracle.multisplit(keys, 256, oracle.SPLITTERS, splitters=spl)
+    dk, ds = dev(keys), dev(spl)
+    say("case range 2^27 fit")
+    gm = ms.learned_fit(dev(fit), ds, 256)
+    say("case range 2^27 learned")
+    k, o = ms.keys(dk, 256, ms.BucketFn.learned(ds, gm))
+    np.testing.assert_array_equal(host(k), ek)
+    np.testing.assert_array_equal(host(o), eo)
+    say("case range 2^27 binary search")
+    k, o = ms.keys(dk, 256, ms.BucketFn.splitter(ds))
+    np.testing.assert_array_equal(host(k), ek)
+    np.testing.assert_array_equal(host(o), eo)
