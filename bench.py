@@ -62,6 +62,10 @@ def workload(name):
         return name.rsplit("_", 1)[0], 1 << 28, 256, 0, 105
     if name == "range_2e27_m256":
         return "range", 1 << 27, 256, 0, 103
+    if name == "copy_2e28":
+        return "copy", 1 << 28, 1, 0, 7
+    if name == "batched_4096_m64":
+        return "batched", 4096, 64, 8, 104
     raise SystemExit("unknown workload %s" % name)
 
 
@@ -187,6 +191,107 @@ def time_steps(step, K, warmup):
     return total, stage
 
 
+def bench_batched(args, num, m, shift, seed, dev):
+    """4096 independent key-value instances, sizes log-uniform in [2^8, 2^20]
+    (seed 104), keys uniform (seed 104000 + i), values = index within the
+    instance, m = 64, f(k) = (k >> 8) & 63; the tuning comes from the
+    autotuner; the call is captured in a HIP graph and the replays are timed."""
+    import numpy as np
+    import torch
+
+    from paper_1701_01189_amd import binding as ms
+    from paper_1701_01189_amd import inputs, tuning
+    sizes = inputs.batched_sizes(seed, num)
+    seg = inputs.segment_offsets(sizes)
+    keys, vals = inputs.batched_pairs(seed, sizes)
+    total = len(keys)
+    dk = torch.from_numpy(keys.view(np.int32)).to(dev)
+    dv = torch.from_numpy(vals.view(np.int32)).to(dev)
+    ds = torch.from_numpy(seg.astype(np.int64)).to(dev)
+    fn = ms.BucketFn.shift_mask(shift, m - 1)
+    if args.reorder or args.waves or args.items:
+        opt = ms.Options(waves_per_block=args.waves, items_per_lane=args.items)
+        tune = {"source": "command line"}
+    else:
+        opt, tune = tuning.tuned_options(ms.OP_BATCHED, dk, dv, m, fn=fn, seg=ds)
+    ko, vo = torch.empty_like(dk), torch.empty_like(dv)
+    off = torch.empty(num * (m + 1), dtype=torch.int32, device=dev)
+    need = ms.workspace_size(ms.OP_BATCHED, total, m, num, opt)
+    ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        ms.batched(dk, dv, ds, m, fn, keys_out=ko, vals_out=vo, offsets=off, options=opt, ws=ws)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        ms.batched(dk, dv, ds, m, fn, keys_out=ko, vals_out=vo, offsets=off, options=opt, ws=ws)
+    for _ in range(args.warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(args.steps):
+        g.replay()
+    t1.record()
+    torch.cuda.synchronize()
+    t = t0.elapsed_time(t1) / args.steps
+    status = ms.batched_status(ws)
+    value = total / (t * 1e-3) / 1e9
+    gbps = 20.0 * total / (t * 1e-3) / 1e9
+    line = {
+        "metric": METRIC, "value": round(value, 3), "unit": "Gpairs/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(t, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "instances": num, "total_pairs": total, "m": m,
+                   "bucket": "(k >> 8) & 63", "seed": seed, "hipgraph": True,
+                   "tuning": {"waves_per_block": opt.waves_per_block,
+                              "items_per_lane": opt.items_per_lane,
+                              "batch_claim": opt.batch_claim}, "tuner": tune},
+        "status": status,
+        "roofline": {"bound": "hbm", "kernel": "batched_kernel (pre-scan and post-scan)",
+                     "achieved": round(gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": round(gbps / HBM_PEAK_GBPS, 4),
+                     "traffic": traffic_for("batched", args.workload, total),
+                     "bytes_per_unit": 20},
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_copy(args, n, dev):
+    """Streaming copy of n words (the measured HBM ceiling, and the known
+    byte count that scales the FETCH_SIZE / WRITE_SIZE counters)."""
+    import torch
+
+    from paper_1701_01189_amd import binding as ms
+    a = torch.ones(n, dtype=torch.int32, device=dev)
+    b = torch.empty_like(a)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        ms.copy_u32(b, a)
+    hev = HipEvents(2)
+    hip = hev.hip
+    import ctypes
+    hip.hipEventRecord.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    torch.cuda.synchronize()
+    hip.hipEventRecord(ctypes.c_void_p(hev.ev[0]), ctypes.c_void_p(stream.cuda_stream))
+    for _ in range(args.steps):
+        ms.copy_u32(b, a)
+    hip.hipEventRecord(ctypes.c_void_p(hev.ev[1]), ctypes.c_void_p(stream.cuda_stream))
+    torch.cuda.synchronize()
+    t = hev.ms(0, 1) / args.steps
+    hev.close()
+    gbps = 8.0 * n / (t * 1e-3) / 1e9
+    print(json.dumps({"metric": "streaming copy GB/s (ceiling probe)", "value": round(gbps, 1),
+                      "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                      "ms_per_step": round(t, 5), "higher_is_better": True, "dtype": "u32",
+                      "data": "synthetic", "config": {"workload": "copy_2e28", "n": n,
+                                                      "bytes_per_launch": 8 * n}}), flush=True)
+
+
 def bench_range(args, n, m, seed, dev):
     import numpy as np
     import torch
@@ -270,6 +375,10 @@ def main():
     dev = torch.device("cuda:0")
     if kind == "range":
         return bench_range(args, n, m, seed, dev)
+    if kind == "copy":
+        return bench_copy(args, n, dev)
+    if kind == "batched":
+        return bench_batched(args, n, m, shift, seed, dev)
     keys = inputs.uniform_u32(seed, n)
     vals = inputs.index_values(n) if kv else None
     dk = torch.from_numpy(keys.view(np.int32)).to(dev)

@@ -132,6 +132,11 @@ enum {
  *   d_mispredicts    LEARNED only, optional device uint64: the number of
  *                    keys whose raw model prediction was wrong is ADDED to
  *                    it (the caller zeroes it).
+ *   batch_claim      ms_batched: work items taken per queue access (1..64).
+ *   spin_limit       ms_batched: polls a post-scan tile makes for its
+ *                    instance's ready flag before giving up (0 = 2^22).
+ *   test_flags       bit 0: ms_batched never raises ready flags, so every
+ *                    wait expires (exercises the timeout path; for tests).
  */
 typedef struct {
   int32_t reorder;
@@ -140,6 +145,9 @@ typedef struct {
   int32_t max_chunks;
   void* const* stage_events;
   uint64_t* d_mispredicts;
+  uint32_t batch_claim;
+  uint32_t spin_limit;
+  uint32_t test_flags;
 } ms_options;
 
 /* Operations for ms_workspace_size(). */
@@ -200,15 +208,17 @@ ms_status ms_radix_sort(const uint32_t* d_keys_in, const uint32_t* d_vals_in,
                         const ms_options* opt, void* stream);
 
 /*
- * Batched stable multisplit: num_inst independent instances in one launch
- * sequence.  Instance i is elements [d_seg[i], d_seg[i+1]) of the
- * concatenated arrays (d_seg: num_inst+1 ascending uint64, device; d_seg[0]
- * is normally 0; the total must be below 2^32).  Each instance is
- * multisplit on its own into the same index range of the outputs.
- * d_offsets: num_inst*(m+1) uint32 or NULL, instance i's bucket starts
- * relative to its own first element (last entry = its size).  d_vals_in and
- * d_vals_out may both be NULL.  The call does not synchronise and allocates
- * nothing, so it can be captured into a HIP graph.
+ * Batched stable multisplit: num_inst independent instances in one
+ * persistent launch (after a one-workgroup set-up kernel).  Instance i is
+ * elements [d_seg[i], d_seg[i+1]) of the concatenated arrays (d_seg:
+ * num_inst+1 ascending uint64 in device memory, d_seg[0] = 0, d_seg[num_inst]
+ * = total < 2^32 - 1).  Each instance is multisplit on its own into the same
+ * index range of the outputs.  d_offsets: num_inst*(m+1) uint32 or NULL,
+ * instance i's bucket starts relative to its own first element (last entry =
+ * its size).  d_vals_in and d_vals_out may both be NULL.  The call neither
+ * synchronises nor allocates and clears its own counters with a kernel, so it
+ * can be captured into a HIP graph and replayed.  Whether any internal wait
+ * expired can be read afterwards with ms_batched_status().
  */
 ms_status ms_batched(const uint32_t* d_keys_in, const uint32_t* d_vals_in,
                      uint32_t* d_keys_out, uint32_t* d_vals_out,
@@ -216,6 +226,13 @@ ms_status ms_batched(const uint32_t* d_keys_in, const uint32_t* d_vals_in,
                      uint32_t m, const ms_bucket_fn* fn, uint32_t* d_offsets,
                      void* d_ws, size_t ws_bytes, const ms_options* opt,
                      void* stream);
+
+/*
+ * Status of the last ms_batched call that used workspace d_ws: MS_OK, or
+ * MS_ERR_TIMEOUT if a post-scan tile gave up waiting for its instance (its
+ * output is then incomplete).  Waits for `stream` (not capture-safe).
+ */
+ms_status ms_batched_status(const void* d_ws, void* stream);
 
 /*
  * Fit the learned bucket model for range buckets given by m-1 ascending
@@ -230,6 +247,25 @@ ms_status ms_learned_fit(const uint32_t* d_sample, size_t n_sample,
                          const uint32_t* d_splitters, uint32_t m,
                          float* d_model, void* d_ws, size_t ws_bytes,
                          void* stream);
+
+/*
+ * Autotuner: runs `op` (MS_OP_KEYS, MS_OP_PAIRS, MS_OP_BATCHED,
+ * MS_OP_RADIX_SORT or MS_OP_RADIX_SORT_PAIRS) on the caller's buffers once
+ * per candidate tuning (reordering mode, waves per workgroup, windows per
+ * wavefront and, for MS_OP_BATCHED, the queue claim size), `reps` timed
+ * times each after one warm-up, and writes the fastest candidate to *best
+ * (fields other than the tuned ones are copied from `base`, which may be
+ * NULL) and its mean time in milliseconds to *best_ms.  The outputs hold the
+ * result of the last run.  Candidates whose workspace exceeds ws_bytes are
+ * skipped.  Arguments as for the operation itself (d_seg / num_inst for
+ * MS_OP_BATCHED only, fn ignored for the radix sort, m = bits per pass for
+ * the radix sort).  Synchronises `stream`; not capture-safe.
+ */
+ms_status ms_autotune(int op, const uint32_t* d_keys_in, const uint32_t* d_vals_in,
+                      uint32_t* d_keys_out, uint32_t* d_vals_out, const uint64_t* d_seg,
+                      uint32_t num_inst, size_t n, uint32_t m, const ms_bucket_fn* fn,
+                      void* d_ws, size_t ws_bytes, int reps, const ms_options* base,
+                      ms_options* best, float* best_ms, void* stream);
 
 /*
  * Streaming copy of n uint32 (d_dst[i] = d_src[i]).  Not part of the

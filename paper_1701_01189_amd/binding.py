@@ -39,12 +39,15 @@ class BucketFnC(ctypes.Structure):
 class OptionsC(ctypes.Structure):
     _fields_ = [("reorder", ctypes.c_int32), ("waves_per_block", ctypes.c_int32),
                 ("items_per_lane", ctypes.c_int32), ("max_chunks", ctypes.c_int32),
-                ("stage_events", ctypes.c_void_p), ("d_mispredicts", ctypes.c_void_p)]
+                ("stage_events", ctypes.c_void_p), ("d_mispredicts", ctypes.c_void_p),
+                ("batch_claim", ctypes.c_uint32), ("spin_limit", ctypes.c_uint32),
+                ("test_flags", ctypes.c_uint32)]
 
 
 _lib = None
 SYMBOLS = ["ms_status_str", "ms_version", "ms_workspace_size", "ms_keys", "ms_pairs",
-           "ms_radix_sort", "ms_batched", "ms_learned_fit", "ms_copy_u32"]
+           "ms_radix_sort", "ms_batched", "ms_batched_status", "ms_learned_fit", "ms_copy_u32",
+           "ms_autotune"]
 
 
 def lib():
@@ -74,6 +77,12 @@ def lib():
     L.ms_batched.argtypes = [vp, vp, vp, vp, vp, u32, sz, u32, ctypes.POINTER(BucketFnC), vp, vp,
                              sz, ctypes.POINTER(OptionsC), vp]
     L.ms_batched.restype = i32
+    L.ms_autotune.argtypes = [i32, vp, vp, vp, vp, vp, u32, sz, u32, ctypes.POINTER(BucketFnC),
+                              vp, sz, i32, ctypes.POINTER(OptionsC), ctypes.POINTER(OptionsC),
+                              ctypes.POINTER(ctypes.c_float), vp]
+    L.ms_autotune.restype = i32
+    L.ms_batched_status.argtypes = [vp, vp]
+    L.ms_batched_status.restype = i32
     L.ms_learned_fit.argtypes = [vp, sz, vp, u32, vp, vp, sz, vp]
     L.ms_learned_fit.restype = i32
     L.ms_copy_u32.argtypes = [vp, vp, sz, vp]
@@ -145,9 +154,11 @@ class Options:
     """Tuning and instrumentation (ms_options); all fields optional."""
 
     def __init__(self, reorder=0, waves_per_block=0, items_per_lane=0, max_chunks=0,
-                 stage_events=None, mispredicts=None):
+                 stage_events=None, mispredicts=None, batch_claim=0, spin_limit=0,
+                 test_flags=0):
         self.reorder, self.waves_per_block = reorder, waves_per_block
         self.items_per_lane, self.max_chunks = items_per_lane, max_chunks
+        self.batch_claim, self.spin_limit, self.test_flags = batch_claim, spin_limit, test_flags
         self.stage_events = stage_events   # list of 4 torch.cuda.Event or None
         self.mispredicts = mispredicts     # 1-element int64 CUDA tensor or None
         self._ev = None
@@ -158,7 +169,8 @@ class Options:
             self._ev = (ctypes.c_void_p * 4)(*[e.cuda_event for e in self.stage_events])
             ev = ctypes.cast(self._ev, ctypes.c_void_p)
         return OptionsC(self.reorder, self.waves_per_block, self.items_per_lane,
-                        self.max_chunks, ev, _ptr(self.mispredicts))
+                        self.max_chunks, ev, _ptr(self.mispredicts), self.batch_claim,
+                        self.spin_limit, self.test_flags)
 
 
 def _opt(options):
@@ -240,6 +252,74 @@ def radix_sort(keys_in, vals_in=None, bits_per_pass=8, keys_out=None, vals_out=N
                              ctypes.byref(o) if o is not None else None, _stream(stream))
     _check(rc, "ms_radix_sort")
     return keys_out, vals_out
+
+
+def batched(keys_in, vals_in, seg, m, fn, keys_out=None, vals_out=None, offsets=None,
+            options=None, stream=None, ws=None):
+    """Batched multisplit of the instances [seg[i], seg[i+1]) of the
+    concatenated inputs.  seg: int64 CUDA tensor of num+1 offsets.  Returns
+    (keys_out, vals_out or None, offsets[num*(m+1)], workspace)."""
+    import torch
+    n = keys_in.numel()
+    num = seg.numel() - 1
+    kv = vals_in is not None
+    if keys_out is None:
+        keys_out = torch.empty_like(keys_in)
+    if kv and vals_out is None:
+        vals_out = torch.empty_like(vals_in)
+    if offsets is None:
+        offsets = torch.empty(max(1, num * (m + 1)), dtype=torch.int32, device=keys_in.device)
+    if seg.element_size() != 8:
+        raise ValueError("seg must hold 64-bit offsets")
+    w, wb = _workspace(OP_BATCHED, n, m, keys_in.device, options, num_inst=num, ws=ws)
+    f = fn.c()
+    o = options.c() if options is not None else None
+    rc = lib().ms_batched(_u32(keys_in, "keys_in"), _u32(vals_in, "vals_in"),
+                          _u32(keys_out, "keys_out"), _u32(vals_out, "vals_out"), _ptr(seg),
+                          num, n, m, ctypes.byref(f), _u32(offsets, "offsets"), _ptr(w), wb,
+                          ctypes.byref(o) if o is not None else None, _stream(stream))
+    _check(rc, "ms_batched")
+    return keys_out, vals_out, offsets, w
+
+
+def autotune(op, keys_in, vals_in, m, fn=None, seg=None, reps=3, base=None, stream=None):
+    """Times every candidate tuning of `op` on these inputs (scratch outputs
+    and workspace are allocated here) and returns (Options, milliseconds)."""
+    import torch
+    n = keys_in.numel()
+    num = seg.numel() - 1 if seg is not None else 0
+    ko = torch.empty_like(keys_in)
+    vo = torch.empty_like(vals_in) if vals_in is not None else None
+    radix = op in (OP_RADIX_SORT, OP_RADIX_SORT_PAIRS)
+    need = 0
+    for wpb, nw, mode in ((8, 8, 1), (8, 4, 1), (4, 8, 1), (4, 16, 1), (8, 8, 2), (4, 16, 2),
+                          (8, 8, 3)):
+        if op == OP_BATCHED and (wpb != 8 or mode != 1):
+            continue
+        need = max(need, workspace_size(op, n, 256 if radix else m, num,
+                                        Options(reorder=mode, waves_per_block=wpb,
+                                                items_per_lane=nw)))
+    ws = torch.empty(max(need, 256), dtype=torch.uint8, device=keys_in.device)
+    best = OptionsC()
+    ms_ = ctypes.c_float(0.0)
+    f = fn.c() if fn is not None else BucketFnC(0, 0, 0, 0, None, None)
+    b = base.c() if base is not None else None
+    rc = lib().ms_autotune(op, _u32(keys_in, "keys_in"), _u32(vals_in, "vals_in"), _u32(ko, "ko"),
+                           _u32(vo, "vo"), _ptr(seg) if seg is not None else None, num, n, m,
+                           ctypes.byref(f), _ptr(ws), ws.numel(), reps,
+                           ctypes.byref(b) if b is not None else None, ctypes.byref(best),
+                           ctypes.byref(ms_), _stream(stream))
+    _check(rc, "ms_autotune")
+    opt = Options(reorder=best.reorder, waves_per_block=best.waves_per_block,
+                  items_per_lane=best.items_per_lane, max_chunks=best.max_chunks,
+                  batch_claim=best.batch_claim, spin_limit=best.spin_limit,
+                  test_flags=best.test_flags)
+    return opt, float(ms_.value)
+
+
+def batched_status(ws, stream=None):
+    """MS_OK or MS_ERR_TIMEOUT for the last batched call on workspace ws."""
+    return int(lib().ms_batched_status(_ptr(ws), _stream(stream)))
 
 
 def learned_fit(sample, splitters, m, model=None, stream=None, ws=None):

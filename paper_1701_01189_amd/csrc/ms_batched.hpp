@@ -1,0 +1,287 @@
+// Batched stable multisplit: many independent instances (segments of one
+// concatenated array) in one persistent launch.  Not in the paper; it uses
+// the paper's per-tile machinery (pre-scan histogram, scan of the
+// row-vectorised H of Eq. 2, post-scan rank/reorder/scatter) with one
+// subproblem per tile.
+//
+// Work items, handed out by one atomic queue counter in this order:
+//   [0, P)      pre-scan of tile t (all tiles of all instances, P in total);
+//   [P, 2P)     post-scan of tile t - P.
+// The last pre-scan tile of an instance to finish (a per-instance atomic
+// counter) scans that instance's H and raises its ready flag; a post-scan
+// tile waits for its instance's flag.  Every pre-scan item is dequeued before
+// any post-scan item, by a workgroup that is already running and never
+// waits, so each awaited flag is eventually raised whatever the residency.
+// The wait is bounded all the same (spin_limit polls); on expiry the tile is
+// skipped and the status word records MS_ERR_TIMEOUT.
+#pragma once
+
+#include "ms_kernels.hpp"
+
+namespace ms {
+
+struct BatchedArgs {
+  const uint32_t* keys_in;
+  const uint32_t* vals_in;
+  uint32_t* keys_out;
+  uint32_t* vals_out;
+  const uint64_t* seg;   // num + 1 segment starts
+  uint32_t num;
+  uint32_t m;
+  uint32_t* offsets;     // num * (m+1)
+  uint32_t* tile_start;  // num + 1: first global tile of each instance
+  uint32_t* tile_inst;   // per global tile: its instance
+  uint32_t* H;           // m * P words; instance i at m * tile_start[i]
+  uint32_t* done;        // num: finished pre-scan tiles
+  uint32_t* ready;       // num: 1 once G of the instance is published
+  uint32_t* ctl;         // [0] queue counter, [1] status
+  uint32_t tile;         // elements per tile
+  uint32_t claim;        // work items per queue claim
+  uint32_t spin_limit;   // polls before a wait gives up
+  uint32_t never_ready;  // test hook: never raise ready flags (forces timeouts)
+  BucketParams bp;
+};
+
+constexpr int kSetupThreads = 1024;
+
+// (Internal linkage: every translation unit that launches it has a copy.)
+// Tiles per instance, their exclusive prefix (tile_start), counters and
+// flags cleared, offsets of empty instances written.  One workgroup.
+static __global__ void __launch_bounds__(kSetupThreads) batched_setup_kernel(BatchedArgs a) {
+  __shared__ uint32_t tmp[kSetupThreads / kWave];
+  const uint32_t lane = lane_id(), w = wave_id();
+  const uint32_t per = (a.num + kSetupThreads - 1) / kSetupThreads;
+  const uint32_t i0 = threadIdx.x * per;
+  uint32_t sum = 0;
+  for (uint32_t e = 0; e < per; ++e) {
+    const uint32_t i = i0 + e;
+    if (i < a.num) {
+      const uint64_t n = a.seg[i + 1] - a.seg[i];
+      sum += (uint32_t)((n + a.tile - 1) / a.tile);
+    }
+  }
+  uint32_t total;
+  uint32_t pre = group_exclusive_scan<kSetupThreads / kWave>(sum, tmp, w, lane, &total);
+  for (uint32_t e = 0; e < per; ++e) {
+    const uint32_t i = i0 + e;
+    if (i < a.num) {
+      const uint64_t n = a.seg[i + 1] - a.seg[i];
+      a.tile_start[i] = pre;
+      pre += (uint32_t)((n + a.tile - 1) / a.tile);
+      a.done[i] = 0;
+      a.ready[i] = 0;
+      if (n == 0)
+        for (uint32_t b = 0; b <= a.m; ++b) a.offsets[(uint64_t)i * (a.m + 1) + b] = 0;
+    }
+  }
+  if (threadIdx.x == 0) {
+    a.tile_start[a.num] = total;
+    a.ctl[0] = 0;
+    a.ctl[1] = 0;
+  }
+  // tile -> instance map (the workgroup's own tile_start writes are visible
+  // after the barrier)
+  __syncthreads();
+  for (uint32_t e = 0; e < per; ++e) {
+    const uint32_t i = i0 + e;
+    if (i < a.num)
+      for (uint32_t t = a.tile_start[i]; t < a.tile_start[i + 1]; ++t) a.tile_inst[t] = i;
+  }
+}
+
+// Exclusive scan in place of E words by one workgroup.
+template <int WPB>
+__device__ void block_scan_inplace(uint32_t* data, uint32_t E, uint32_t* tmp) {
+  constexpr int PER = 4;
+  const uint32_t lane = lane_id(), w = wave_id();
+  uint32_t carry = 0;
+  for (uint32_t base = 0; base < E; base += WPB * kWave * PER) {
+    uint32_t v[PER], s = 0;
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const uint32_t i = base + threadIdx.x * PER + e;
+      v[e] = i < E ? data[i] : 0u;
+      s += v[e];
+    }
+    uint32_t total;
+    uint32_t pre = group_exclusive_scan<WPB>(s, tmp, w, lane, &total) + carry;
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const uint32_t i = base + threadIdx.x * PER + e;
+      if (i < E) data[i] = pre;
+      pre += v[e];
+    }
+    carry += total;
+  }
+}
+
+template <int Kind, int BITS, bool KV, int WPB, int NW>
+__global__ void __launch_bounds__(WPB* kWave) batched_kernel(BatchedArgs a) {
+  constexpr int T = WPB * NW * kWave;
+  constexpr int MB = Owned<BITS>::value;
+  __shared__ BucketLds tables;
+  __shared__ uint32_t s_cnt[WPB * kCntStride];
+  __shared__ uint32_t s_run[kMaxBuckets];
+  __shared__ uint32_t s_delta[kMaxBuckets];
+  __shared__ uint32_t s_keys[T];
+  __shared__ uint32_t s_vals[KV ? T : 1];
+  __shared__ uint8_t s_bk[T];
+  __shared__ uint32_t s_tmp[WPB];
+  __shared__ uint32_t s_next, s_flag;
+
+  stage_bucket_tables<Kind>(a.bp, &tables);
+  __syncthreads();
+  Bucket<Kind, BITS> bf_pre(a.bp, &tables);
+  Bucket<Kind, BITS> bf_post(a.bp, &tables);
+  const uint32_t lane = lane_id(), w = wave_id();
+  const uint32_t tid = threadIdx.x;
+  const LaneSel ls(lane);
+  const uint32_t m = a.m;
+  const uint32_t P = a.tile_start[a.num];
+  const uint32_t items = 2 * P;
+  const uint32_t wbase = w * NW * kWave;
+
+  // The next claim is taken from the queue while the current one is worked
+  // on, so the atomic's latency is hidden.
+  if (tid == 0)
+    s_next = __hip_atomic_fetch_add(a.ctl, a.claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (;;) {
+    __syncthreads();
+    const uint32_t first = s_next;
+    __syncthreads();
+    if (first >= items) break;
+    if (tid == 0)
+      s_next = __hip_atomic_fetch_add(a.ctl, a.claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t last = min(items, first + a.claim);
+
+    // ---- pre-scan items of this claim: one column of H per tile; the
+    // columns of one instance are published together (one release) ----
+    uint32_t pub_inst = 0xFFFFFFFFu, pub_count = 0;
+    auto publish = [&]() {
+      __syncthreads();
+      if (tid == 0) {
+        const uint32_t tiles = a.tile_start[pub_inst + 1] - a.tile_start[pub_inst];
+        const uint32_t prev = __hip_atomic_fetch_add(a.done + pub_inst, pub_count, __ATOMIC_ACQ_REL,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+        s_flag = (prev + pub_count == tiles) ? 1u : 0u;
+      }
+      __syncthreads();
+      if (s_flag) {
+        // the instance's last columns: scan its H into G and publish G
+        const uint32_t i = pub_inst;
+        const uint32_t tiles = a.tile_start[i + 1] - a.tile_start[i];
+        uint32_t* Hi = a.H + (size_t)m * a.tile_start[i];
+        block_scan_inplace<WPB>(Hi, m * tiles, s_tmp);
+        __syncthreads();
+        for (uint32_t b = tid; b < m; b += WPB * kWave)
+          a.offsets[(size_t)i * (m + 1) + b] = Hi[b * tiles];
+        if (tid == 0) a.offsets[(size_t)i * (m + 1) + m] = (uint32_t)(a.seg[i + 1] - a.seg[i]);
+        __syncthreads();
+        if (tid == 0 && !a.never_ready)
+          __hip_atomic_store(a.ready + i, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      __syncthreads();
+    };
+    for (uint32_t it = first; it < min(last, P); ++it) {
+      const uint32_t i = a.tile_inst[it];
+      if (i != pub_inst) {
+        if (pub_count) publish();
+        pub_inst = i;
+        pub_count = 0;
+      }
+      const uint32_t t = it - a.tile_start[i];
+      const uint32_t tiles = a.tile_start[i + 1] - a.tile_start[i];
+      const uint32_t n_i = (uint32_t)(a.seg[i + 1] - a.seg[i]);
+      const uint32_t tcount = min((uint32_t)T, n_i - t * T);
+      const uint32_t tb = (uint32_t)a.seg[i] + t * T;
+      uint32_t* Hi = a.H + (size_t)m * a.tile_start[i];
+      uint32_t cnt[MB];
+#pragma unroll
+      for (int q = 0; q < MB; ++q) cnt[q] = 0;
+      const uint32_t* pk = a.keys_in + tb + wbase + lane;
+#pragma unroll
+      for (int j = 0; j < NW; ++j) {
+        const bool valid = wbase + (uint32_t)(j * kWave) + lane < tcount;
+        const uint32_t b = valid ? bf_pre(pk[j * kWave]) : 0u;
+        window_histogram<BITS>(b, ballot(valid), ls, cnt);
+      }
+#pragma unroll
+      for (int q = 0; q < MB; ++q) {
+        const uint32_t b = lane + kWave * q;
+        if (b < m) s_cnt[w * kCntStride + b] = cnt[q];
+      }
+      __syncthreads();
+      for (uint32_t b = tid; b < m; b += WPB * kWave) {
+        uint32_t s = 0;
+#pragma unroll
+        for (int ww = 0; ww < WPB; ++ww) s += s_cnt[ww * kCntStride + b];
+        Hi[b * tiles + t] = s;
+      }
+      __syncthreads();
+      ++pub_count;
+    }
+    if (pub_count) publish();
+
+    // ---- post-scan items of this claim; the wait (an acquire) is done
+    // once per instance ----
+    uint32_t seen = 0xFFFFFFFFu;
+    for (uint32_t it = (first > P ? first : P); it < last; ++it) {
+      const uint32_t tg = it - P;
+      const uint32_t i = a.tile_inst[tg];
+      if (i != seen) {
+        if (tid == 0) {
+          uint32_t ok = 1, polls = 0;
+          while (__hip_atomic_load(a.ready + i, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
+            if (++polls > a.spin_limit) {
+              ok = 0;
+              __hip_atomic_fetch_or(a.ctl + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+          }
+          s_flag = ok;
+        }
+        __syncthreads();
+        seen = s_flag ? i : 0xFFFFFFFFu;
+        if (!s_flag) {
+          __syncthreads();
+          continue;  // instance not published in time: tile skipped, status set
+        }
+      }
+      const uint32_t t = tg - a.tile_start[i];
+      const uint32_t tiles = a.tile_start[i + 1] - a.tile_start[i];
+      const uint32_t s0 = (uint32_t)a.seg[i];
+      const uint32_t n_i = (uint32_t)(a.seg[i + 1] - s0);
+      const uint32_t tcount = min((uint32_t)T, n_i - t * T);
+      const uint32_t tb = s0 + t * T;
+      const uint32_t* Hi = a.H + (size_t)m * a.tile_start[i];
+      for (uint32_t b = tid; b < m; b += WPB * kWave) s_run[b] = s0 + Hi[b * tiles + t];
+      uint32_t k[NW], v[NW];
+      const uint32_t* pk = a.keys_in + tb + wbase + lane;
+      const uint32_t* pv = a.vals_in + tb + wbase + lane;
+#pragma unroll
+      for (int j = 0; j < NW; ++j) {
+        // lanes past the end read the tile's first element, which exists
+        const bool valid = wbase + (uint32_t)(j * kWave) + lane < tcount;
+        k[j] = __builtin_nontemporal_load(valid ? pk + j * kWave : a.keys_in + tb);
+        if (KV) v[j] = __builtin_nontemporal_load(valid ? pv + j * kWave : a.vals_in + tb);
+      }
+      __syncthreads();
+      TileCtx<KV> ctx{s_keys, s_vals, s_bk, s_cnt + w * kCntStride, s_cnt, s_run, s_delta,
+                      s_tmp, a.keys_out, a.vals_out, m, tcount, w, lane, tid};
+      if (tcount == (uint32_t)T)
+        tile_rank_reorder_write<BITS, KV, WPB, NW, true>(bf_post, k, v, ctx, [] {});
+      else
+        tile_rank_reorder_write<BITS, KV, WPB, NW, false>(bf_post, k, v, ctx, [] {});
+      __syncthreads();
+    }
+  }
+  if (Kind == kLearned && a.bp.mispredicts) {
+    uint32_t miss = bf_post.misses();
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) miss += __shfl_xor(miss, d, kWave);
+    if (lane == 0 && miss) atomicAdd(a.bp.mispredicts, (unsigned long long)miss);
+  }
+}
+
+}  // namespace ms

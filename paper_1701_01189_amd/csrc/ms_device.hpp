@@ -27,6 +27,11 @@ __device__ __forceinline__ uint64_t ballot(bool p) {
   return __builtin_amdgcn_ballot_w64(p);
 }
 
+// Index of this wavefront in its workgroup, as a wavefront-uniform value.
+__device__ __forceinline__ uint32_t wave_id() {
+  return __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+}
+
 __device__ __forceinline__ uint32_t lane_id() {
   return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
 }
@@ -277,17 +282,6 @@ __device__ __forceinline__ void stage_bucket_tables(const BucketParams& p, Bucke
     for (uint32_t i = threadIdx.x; i < (uint32_t)kModelFloats; i += blockDim.x)
       l->model[i] = p.model[i];
   }
-}
-
-// XCD-aware placement: workgroups are dispatched round-robin over the 8
-// accelerator dies, each with its own L2.  Map workgroup i to a chunk so that
-// the workgroups of one die get consecutive chunks; neighbouring chunks then
-// share the cache lines at their output boundaries inside one L2.
-__device__ __forceinline__ uint32_t xcd_chunk(uint32_t bid, uint32_t grid) {
-  const uint32_t X = 8;
-  uint32_t x = bid % X, r = bid / X;
-  uint32_t q = grid / X, rem = grid % X;
-  return x * q + (x < rem ? x : rem) + r;
 }
 
 }  // namespace ms

@@ -5,6 +5,7 @@
 // instantiates its share (ms_kind_*.hip).
 #pragma once
 
+#include "ms_batched.hpp"
 #include "ms_kernels.hpp"
 
 namespace ms {
@@ -123,6 +124,52 @@ hipError_t post_dispatch(const PostArgs& a, int bits) {
   }
 }
 
+// Batched: shapes (waves per block, windows) with an instantiated kernel.
+inline bool batched_shape_supported(int wpb, int nw) {
+  return wpb == 8 && (nw == 8 || nw == 4);
+}
+
+template <int Kind, int BITS, bool KV, int WPB, int NW>
+hipError_t batched_launch(const BatchedArgs& a, hipStream_t st) {
+  auto kern = batched_kernel<Kind, BITS, KV, WPB, NW>;
+  int per_cu = 0, dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return hipErrorInvalidDevice;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return hipErrorInvalidDevice;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, WPB * kWave, 0) != hipSuccess)
+    return hipErrorInvalidValue;
+  if (per_cu < 1) per_cu = 1;
+  hipLaunchKernelGGL(batched_setup_kernel, dim3(1), dim3(kSetupThreads), 0, st, a);
+  hipLaunchKernelGGL(kern, dim3(per_cu * cus), dim3(WPB * kWave), 0, st, a);
+  return hipGetLastError();
+}
+
+template <int Kind, int BITS>
+hipError_t batched_shape(const BatchedArgs& a, bool kv, int wpb, int nw, hipStream_t st) {
+  if (wpb == 8 && nw == 8)
+    return kv ? batched_launch<Kind, BITS, true, 8, 8>(a, st) : batched_launch<Kind, BITS, false, 8, 8>(a, st);
+  if (wpb == 8 && nw == 4)
+    return kv ? batched_launch<Kind, BITS, true, 8, 4>(a, st) : batched_launch<Kind, BITS, false, 8, 4>(a, st);
+  return hipErrorInvalidValue;
+}
+
+template <int Kind>
+hipError_t batched_dispatch(const BatchedArgs& a, int bits, bool kv, int wpb, int nw,
+                            hipStream_t st) {
+  switch (bits) {
+    case 0: return batched_shape<Kind, 0>(a, kv, wpb, nw, st);
+    case 1: return batched_shape<Kind, 1>(a, kv, wpb, nw, st);
+    case 2: return batched_shape<Kind, 2>(a, kv, wpb, nw, st);
+    case 3: return batched_shape<Kind, 3>(a, kv, wpb, nw, st);
+    case 4: return batched_shape<Kind, 4>(a, kv, wpb, nw, st);
+    case 5: return batched_shape<Kind, 5>(a, kv, wpb, nw, st);
+    case 6: return batched_shape<Kind, 6>(a, kv, wpb, nw, st);
+    case 7: return batched_shape<Kind, 7>(a, kv, wpb, nw, st);
+    case 8: return batched_shape<Kind, 8>(a, kv, wpb, nw, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 // Entry points defined in the per-kind translation units.
 hipError_t pre_shift_mask(const PreArgs& a, int bits);
 hipError_t pre_div(const PreArgs& a, int bits);
@@ -132,5 +179,9 @@ hipError_t post_shift_mask(const PostArgs& a, int bits);
 hipError_t post_div(const PostArgs& a, int bits);
 hipError_t post_splitters(const PostArgs& a, int bits);
 hipError_t post_learned(const PostArgs& a, int bits);
+hipError_t batched_shift_mask(const BatchedArgs& a, int bits, bool kv, int wpb, int nw, hipStream_t st);
+hipError_t batched_div(const BatchedArgs& a, int bits, bool kv, int wpb, int nw, hipStream_t st);
+hipError_t batched_splitters(const BatchedArgs& a, int bits, bool kv, int wpb, int nw, hipStream_t st);
+hipError_t batched_learned(const BatchedArgs& a, int bits, bool kv, int wpb, int nw, hipStream_t st);
 
 }  // namespace ms

@@ -88,9 +88,9 @@ prescan_kernel(const uint32_t* __restrict__ keys, Plan plan, BucketParams bp,
 
   const uint32_t lane = lane_id();
   const LaneSel ls(lane);
-  const uint32_t w = threadIdx.x / kWave;
+  const uint32_t w = wave_id();
   const uint32_t g = w / WPG, wg = w % WPG;
-  const uint32_t c = (GPB == 1 ? xcd_chunk(blockIdx.x, gridDim.x) : blockIdx.x * GPB + g);
+  const uint32_t c = blockIdx.x * GPB + g;
   uint32_t cnt[MB];
 #pragma unroll
   for (int t = 0; t < MB; ++t) cnt[t] = 0;
@@ -165,6 +165,115 @@ prescan_kernel(const uint32_t* __restrict__ keys, Plan plan, BucketParams bp,
 }
 
 // ---------------------------------------------------------------------------
+// One tile of the post-scan (steps 2-5 below) for a group of WPG wavefronts
+// whose keys (and values) are already in registers k, v: element (wave wg,
+// window j, lane) of the tile is k[j] of that lane.  run[b] holds the output
+// position of the tile's first bucket-b element and is advanced past the
+// tile's bucket-b elements.  `after_stage` runs once k, v are no longer
+// needed (used to issue the next tile's loads early).
+// ---------------------------------------------------------------------------
+template <bool KV>
+struct TileCtx {
+  uint32_t* s_k;       // LDS reorder buffer: keys
+  uint32_t* s_v;       // LDS reorder buffer: values
+  uint8_t* s_b;        // LDS reorder buffer: bucket ids
+  uint32_t* my_cnt;    // this wavefront's counters [bucket]
+  uint32_t* grp_cnt;   // the group's counters [wave][bucket], stride CNT_STRIDE
+  uint32_t* run;       // [bucket] output position of the next element
+  uint32_t* delta;     // [bucket] scratch: output position minus LDS slot
+  uint32_t* tmp;       // WPG words for the group scan
+  uint32_t* keys_out;
+  uint32_t* vals_out;
+  uint32_t m, tcount, wg, lane, tid_g;
+};
+
+constexpr int kCntStride = kMaxBuckets + 1;
+
+template <int BITS, bool KV, int WPG, int NW, bool FULL, class BF, class AfterStage>
+__device__ __forceinline__ void tile_rank_reorder_write(const BF& bf, uint32_t (&k)[NW],
+                                                        uint32_t (&v)[NW], const TileCtx<KV>& c,
+                                                        AfterStage after_stage) {
+  const uint32_t m = c.m, tcount = c.tcount, lane = c.lane, wg = c.wg, tid_g = c.tid_g;
+  const uint32_t wbase = wg * NW * kWave;
+  for (uint32_t b = lane; b < m; b += kWave) lds_put(c.my_cnt + b, 0u);
+  uint32_t bk[NW], lr[NW];
+#pragma unroll
+  for (int j = 0; j < NW; ++j) {
+    const bool valid = FULL || wbase + (uint32_t)(j * kWave) + lane < tcount;
+    bk[j] = valid ? bf(k[j]) : 0u;
+  }
+  wave_order();
+  // ranking: Algorithm 3 per window + per-wavefront running counts
+#pragma unroll
+  for (int j = 0; j < NW; ++j) {
+    const bool valid = FULL || wbase + (uint32_t)(j * kWave) + lane < tcount;
+    const uint64_t mm = match_bucket<BITS>(bk[j], FULL ? ~0ull : ballot(valid));
+    const uint32_t r = count_below(mm), cnt = popc64(mm);
+    const uint32_t before = lds_get(c.my_cnt + bk[j]);
+    lr[j] = before + r;
+    if (valid && r + 1 == cnt) lds_put(c.my_cnt + bk[j], before + cnt);
+    wave_order();
+  }
+  group_sync<WPG>();
+  // exclusive scan of the bucket-major table: entry e = b*WPG + wave
+  {
+    const uint32_t E = m * WPG;
+    const uint32_t ept = (E + WPG * kWave - 1) / (WPG * kWave);
+    const uint32_t e0 = tid_g * ept;
+    uint32_t vals[4];
+    uint32_t s = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t e = e0 + i;
+      vals[i] = ((uint32_t)i < ept && e < E) ? c.grp_cnt[(e % WPG) * kCntStride + e / WPG] : 0u;
+      s += vals[i];
+    }
+    uint32_t total;
+    uint32_t pre = group_exclusive_scan<WPG>(s, c.tmp, wg, lane, &total);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t e = e0 + i;
+      if ((uint32_t)i < ept && e < E) c.grp_cnt[(e % WPG) * kCntStride + e / WPG] = pre;
+      pre += vals[i];
+    }
+  }
+  group_sync<WPG>();
+  // tile bucket starts -> output delta; advance the running bases
+  for (uint32_t b = tid_g; b < m; b += WPG * kWave) {
+    const uint32_t st = c.grp_cnt[b];
+    const uint32_t nx = (b + 1 < m) ? c.grp_cnt[b + 1] : tcount;
+    c.delta[b] = c.run[b] - st;
+    c.run[b] += nx - st;
+  }
+  // local reorder: slot = tile base of (bucket, wavefront) + rank
+#pragma unroll
+  for (int j = 0; j < NW; ++j) {
+    const bool valid = FULL || wbase + (uint32_t)(j * kWave) + lane < tcount;
+    if (valid) {
+      const uint32_t slot = c.my_cnt[bk[j]] + lr[j];
+      c.s_k[slot] = k[j];
+      if (KV) c.s_v[slot] = v[j];
+      c.s_b[slot] = (uint8_t)bk[j];
+    }
+  }
+  group_sync<WPG>();
+  after_stage();
+  // coalesced write-back: consecutive slots of a bucket are consecutive
+  // output positions
+#pragma unroll
+  for (int j = 0; j < NW; ++j) {
+    const uint32_t q = j * (WPG * kWave) + tid_g;
+    if (FULL || q < tcount) {
+      const uint32_t b = c.s_b[q];
+      const uint32_t o = c.delta[b] + q;
+      c.keys_out[o] = c.s_k[q];
+      if (KV) c.vals_out[o] = c.s_v[q];
+    }
+  }
+  group_sync<WPG>();
+}
+
+// ---------------------------------------------------------------------------
 // Post-scan (Algorithm 1's post-scan, Sections 5.5.3-5.6).
 //
 // For every tile of the group's chunk:
@@ -195,7 +304,7 @@ postscan_kernel(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict
   constexpr int GPB = WPB / WPG;
   constexpr int T = WPG * NW * kWave;
   constexpr bool REORDER = (MODE != kDirect);
-  constexpr int CNT_STRIDE = kMaxBuckets + 1;
+  constexpr int CNT_STRIDE = kCntStride;
 
   __shared__ BucketLds tables;
   __shared__ uint32_t s_cnt[WPB * CNT_STRIDE];           // per wavefront counts
@@ -207,7 +316,7 @@ postscan_kernel(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict
   __shared__ uint32_t s_tmp[WPB];
 
   const uint32_t lane = lane_id();
-  const uint32_t w = threadIdx.x / kWave;
+  const uint32_t w = wave_id();
   const uint32_t g = w / WPG, wg = w % WPG;
   const uint32_t tid_g = wg * kWave + lane;
   const uint32_t m = plan.m;
@@ -229,14 +338,14 @@ postscan_kernel(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < GPB * m; i += WPB * kWave) {
       uint32_t gg = i / m, b = i % m;
-      uint32_t cc = (GPB == 1 ? xcd_chunk(blockIdx.x, gridDim.x) : blockIdx.x * GPB + gg);
+      uint32_t cc = blockIdx.x * GPB + gg;
       s_run[gg * kMaxBuckets + b] = (cc < plan.L0) ? s_cnt[b] + G[b * plan.L0 + cc] : 0u;
     }
     __syncthreads();
   }
 
   Bucket<Kind, BITS> bf(bp, &tables);
-  const uint32_t c = (GPB == 1 ? xcd_chunk(blockIdx.x, gridDim.x) : blockIdx.x * GPB + g);
+  const uint32_t c = blockIdx.x * GPB + g;
   if (c >= plan.L0) return;  // only whole idle groups leave (never a BMS group)
   const uint32_t c0 = c * plan.chunk;
   const uint32_t len = min(plan.chunk, plan.n - c0);
@@ -315,90 +424,13 @@ postscan_kernel(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict
         load(ti, std::false_type{});
     };
 
-    // One tile whose keys (and values) are already in k, v.  The loads of
-    // the next tile are issued once k, v have been written to LDS, so they
-    // overlap the write-back of this tile.
     auto tile = [&](uint32_t ti, auto full_tag) {
       constexpr bool FULL = decltype(full_tag)::value;
       const uint32_t tcount = FULL ? (uint32_t)T : min((uint32_t)T, len - ti * T);
-      for (uint32_t b = lane; b < m; b += kWave) lds_put(my_cnt + b, 0u);
-      uint32_t bk[NW], lr[NW];
-#pragma unroll
-      for (int j = 0; j < NW; ++j) {
-        const bool valid = FULL || wbase + (uint32_t)(j * kWave) + lane < tcount;
-        bk[j] = valid ? bf(k[j]) : 0u;
-      }
-      wave_order();
-      // ranking: Algorithm 3 per window + per-wavefront running counts
-#pragma unroll
-      for (int j = 0; j < NW; ++j) {
-        const bool valid = FULL || wbase + (uint32_t)(j * kWave) + lane < tcount;
-        const uint64_t mm = match_bucket<BITS>(bk[j], FULL ? ~0ull : ballot(valid));
-        const uint32_t r = count_below(mm), cnt = popc64(mm);
-        const uint32_t before = lds_get(my_cnt + bk[j]);
-        lr[j] = before + r;
-        if (valid && r + 1 == cnt) lds_put(my_cnt + bk[j], before + cnt);
-        wave_order();
-      }
-      group_sync<WPG>();
-      // exclusive scan of the bucket-major table: entry e = b*WPG + wave
-      {
-        const uint32_t E = m * WPG;
-        const uint32_t ept = (E + WPG * kWave - 1) / (WPG * kWave);
-        const uint32_t e0 = tid_g * ept;
-        uint32_t vals[4];
-        uint32_t s = 0;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const uint32_t e = e0 + i;
-          vals[i] = ((uint32_t)i < ept && e < E) ? grp_cnt[(e % WPG) * CNT_STRIDE + e / WPG] : 0u;
-          s += vals[i];
-        }
-        uint32_t total;
-        uint32_t pre = group_exclusive_scan<WPG>(s, s_tmp + g * WPG, wg, lane, &total);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const uint32_t e = e0 + i;
-          if ((uint32_t)i < ept && e < E) grp_cnt[(e % WPG) * CNT_STRIDE + e / WPG] = pre;
-          pre += vals[i];
-        }
-      }
-      group_sync<WPG>();
-      // tile bucket starts -> output delta; advance the running bases
-      for (uint32_t b = tid_g; b < m; b += WPG * kWave) {
-        const uint32_t st = grp_cnt[b];
-        const uint32_t nx = (b + 1 < m) ? grp_cnt[b + 1] : tcount;
-        delta[b] = run[b] - st;
-        run[b] += nx - st;
-      }
-      // local reorder: slot = tile base of (bucket, wavefront) + rank
-#pragma unroll
-      for (int j = 0; j < NW; ++j) {
-        const bool valid = FULL || wbase + (uint32_t)(j * kWave) + lane < tcount;
-        if (valid) {
-          const uint32_t slot = my_cnt[bk[j]] + lr[j];
-          s_k[slot] = k[j];
-          if (KV) s_v[slot] = v[j];
-          s_b[slot] = (uint8_t)bk[j];
-        }
-      }
-      group_sync<WPG>();
-      if (ti + 1 < ntiles) load_tile(ti + 1);
-      // coalesced write-back: consecutive slots of a bucket are consecutive
-      // output positions
-#pragma unroll
-      for (int j = 0; j < NW; ++j) {
-        const uint32_t q = j * (WPG * kWave) + tid_g;
-        if (FULL || q < tcount) {
-          const uint32_t b = s_b[q];
-          const uint32_t o = delta[b] + q;
-          if (o < plan.n) {
-            keys_out[o] = s_k[q];
-            if (KV) vals_out[o] = s_v[q];
-          }
-        }
-      }
-      group_sync<WPG>();
+      TileCtx<KV> ctx{s_k, s_v, s_b, my_cnt, grp_cnt, run, delta, s_tmp + g * WPG,
+                      keys_out, vals_out, m, tcount, wg, lane, tid_g};
+      tile_rank_reorder_write<BITS, KV, WPG, NW, FULL>(
+          bf, k, v, ctx, [&] { if (ti + 1 < ntiles) load_tile(ti + 1); });
     };
 
     if (ntiles > 0) load_tile(0);

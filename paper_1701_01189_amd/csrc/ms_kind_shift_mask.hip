@@ -5,4 +5,7 @@
 namespace ms {
 hipError_t pre_shift_mask(const PreArgs& a, int bits) { return pre_dispatch<kShiftMask>(a, bits); }
 hipError_t post_shift_mask(const PostArgs& a, int bits) { return post_dispatch<kShiftMask>(a, bits); }
+hipError_t batched_shift_mask(const BatchedArgs& a, int bits, bool kv, int wpb, int nw, hipStream_t st) {
+  return batched_dispatch<kShiftMask>(a, bits, kv, wpb, nw, st);
+}
 }  // namespace ms

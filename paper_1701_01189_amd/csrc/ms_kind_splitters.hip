@@ -5,4 +5,7 @@
 namespace ms {
 hipError_t pre_splitters(const PreArgs& a, int bits) { return pre_dispatch<kSplitters>(a, bits); }
 hipError_t post_splitters(const PostArgs& a, int bits) { return post_dispatch<kSplitters>(a, bits); }
+hipError_t batched_splitters(const BatchedArgs& a, int bits, bool kv, int wpb, int nw, hipStream_t st) {
+  return batched_dispatch<kSplitters>(a, bits, kv, wpb, nw, st);
+}
 }  // namespace ms

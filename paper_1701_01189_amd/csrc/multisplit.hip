@@ -205,6 +205,81 @@ hipError_t fill(uint32_t* p, uint32_t n, uint32_t v, hipStream_t st) {
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// batched multisplit: shape, workspace
+// ---------------------------------------------------------------------------
+struct BatchShape {
+  int wpb, nw;
+  uint32_t tile, claim, spin_limit, never_ready;
+};
+
+int resolve_batch_shape(const ms_options* opt, BatchShape* b) {
+  b->wpb = 8;
+  b->nw = 8;
+  b->claim = 16;
+  b->spin_limit = 1u << 22;
+  b->never_ready = 0;
+  if (opt) {
+    if (opt->waves_per_block) b->wpb = opt->waves_per_block;
+    if (opt->items_per_lane) b->nw = opt->items_per_lane;
+    if (opt->batch_claim) b->claim = opt->batch_claim;
+    if (opt->spin_limit) b->spin_limit = opt->spin_limit;
+    b->never_ready = opt->test_flags & 1u;
+    if (opt->reorder != MS_REORDER_AUTO && opt->reorder != MS_REORDER_BLOCK) return MS_ERR_UNSUPPORTED;
+  }
+  if (b->claim > 64) return MS_ERR_INVALID_ARG;
+  if (!ms::batched_shape_supported(b->wpb, b->nw)) return MS_ERR_UNSUPPORTED;
+  b->tile = (uint32_t)(b->wpb * b->nw * ms::kWave);
+  return MS_OK;
+}
+
+struct BatchWorkspace {
+  uint32_t* ctl;
+  uint32_t* tile_start;
+  uint32_t* tile_inst;
+  uint32_t* done;
+  uint32_t* ready;
+  uint32_t* offsets;
+  uint32_t* H;
+};
+
+// [ctl: 2 words | tile_start: num+1 | tile_inst: tiles | done: num |
+//  ready: num | spare offsets: num*(m+1) | H: m x tiles words], with
+// tiles = total/tile + num bounding the number of tiles.
+size_t batch_layout(size_t total, uint32_t m, uint32_t num, const BatchShape& bs,
+                    BatchWorkspace* w, char* base) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += align_up(bytes, kWsAlign);
+    return o;
+  };
+  size_t o_ctl = take(64);
+  size_t o_ts = take(((size_t)num + 1) * 4);
+  size_t tiles = (total + bs.tile - 1) / bs.tile + num;
+  size_t o_ti = take(tiles * 4);
+  size_t o_done = take((size_t)num * 4);
+  size_t o_ready = take((size_t)num * 4);
+  size_t o_off = take((size_t)num * (m + 1) * 4);
+  size_t o_h = take((size_t)m * tiles * 4);
+  if (w && base) {
+    w->ctl = (uint32_t*)(base + o_ctl);
+    w->tile_start = (uint32_t*)(base + o_ts);
+    w->tile_inst = (uint32_t*)(base + o_ti);
+    w->done = (uint32_t*)(base + o_done);
+    w->ready = (uint32_t*)(base + o_ready);
+    w->offsets = (uint32_t*)(base + o_off);
+    w->H = (uint32_t*)(base + o_h);
+  }
+  return off;
+}
+
+BatchWorkspace carve_batch(void* ws, size_t total, uint32_t m, uint32_t num, const BatchShape& bs) {
+  BatchWorkspace w;
+  batch_layout(total, m, num, bs, &w, (char*)ws);
+  return w;
+}
+
 // The three stages for one multisplit on already validated arguments.
 ms_status run_multisplit(const uint32_t* ki, const uint32_t* vi, uint32_t* ko, uint32_t* vo,
                          uint32_t* offsets, size_t n, uint32_t m, const ms_bucket_fn* fn,
@@ -286,6 +361,12 @@ size_t ms_workspace_size(int op, size_t n, uint32_t m, uint32_t num_inst, const 
       bool kv = op == MS_OP_RADIX_SORT_PAIRS;
       size_t data = align_up(n * 4, kWsAlign) * (kv ? 2 : 1);
       return data + ms_ws_bytes(make_plan(n, 256, s, kv));
+    }
+    case MS_OP_BATCHED: {
+      if (m < 1 || m > (uint32_t)ms::kMaxBuckets || n >= 0xFFFFFFFFull || num_inst == 0) return 0;
+      BatchShape bs;
+      if (resolve_batch_shape(opt, &bs) != MS_OK) return 0;
+      return batch_layout(n, m, num_inst, bs, nullptr, nullptr);
     }
     case MS_OP_LEARNED_FIT: {
       if (n == 0 || n >= 0xFFFFFFFFull) return 0;
@@ -381,10 +462,60 @@ ms_status ms_batched(const uint32_t* d_keys_in, const uint32_t* d_vals_in, uint3
                      uint32_t* d_vals_out, const uint64_t* d_seg, uint32_t num_inst, size_t total,
                      uint32_t m, const ms_bucket_fn* fn, uint32_t* d_offsets, void* d_ws,
                      size_t ws_bytes, const ms_options* opt, void* stream) {
-  (void)d_keys_in; (void)d_vals_in; (void)d_keys_out; (void)d_vals_out; (void)d_seg;
-  (void)num_inst; (void)total; (void)m; (void)fn; (void)d_offsets; (void)d_ws; (void)ws_bytes;
-  (void)opt; (void)stream;
-  return MS_ERR_UNSUPPORTED;
+  const bool kv = d_vals_in != nullptr || d_vals_out != nullptr;
+  ms_status rc = check_common(d_keys_in, d_vals_in, d_keys_out, d_vals_out, total, m, kv);
+  if (rc != MS_OK) return rc;
+  if (num_inst == 0) return MS_OK;
+  if (!d_seg) return MS_ERR_INVALID_ARG;
+  int fr = validate_fn(fn, m);
+  if (fr != MS_OK) return (ms_status)fr;
+  BatchShape bs;
+  int sr = resolve_batch_shape(opt, &bs);
+  if (sr != MS_OK) return (ms_status)sr;
+  const size_t need = ms_workspace_size(MS_OP_BATCHED, total, m, num_inst, opt);
+  if (!d_ws || ws_bytes < need) return MS_ERR_WORKSPACE;
+  BatchWorkspace w = carve_batch(d_ws, total, m, num_inst, bs);
+  ms::BatchedArgs a;
+  memset(&a, 0, sizeof(a));
+  a.keys_in = d_keys_in;
+  a.vals_in = kv ? d_vals_in : nullptr;
+  a.keys_out = d_keys_out;
+  a.vals_out = kv ? d_vals_out : nullptr;
+  a.seg = d_seg;
+  a.num = num_inst;
+  a.m = m;
+  a.offsets = d_offsets ? d_offsets : w.offsets;
+  a.tile_start = w.tile_start;
+  a.tile_inst = w.tile_inst;
+  a.H = w.H;
+  a.done = w.done;
+  a.ready = w.ready;
+  a.ctl = w.ctl;
+  a.tile = bs.tile;
+  a.claim = bs.claim;
+  a.spin_limit = bs.spin_limit;
+  a.never_ready = bs.never_ready;
+  a.bp = make_params(fn, m, opt ? opt->d_mispredicts : nullptr);
+  const int bits = (int)ceil_log2(m);
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e;
+  switch (fn->kind) {
+    case MS_BUCKET_SHIFT_MASK: e = ms::batched_shift_mask(a, bits, kv, bs.wpb, bs.nw, st); break;
+    case MS_BUCKET_DIV: e = ms::batched_div(a, bits, kv, bs.wpb, bs.nw, st); break;
+    case MS_BUCKET_SPLITTERS: e = ms::batched_splitters(a, bits, kv, bs.wpb, bs.nw, st); break;
+    default: e = ms::batched_learned(a, bits, kv, bs.wpb, bs.nw, st); break;
+  }
+  return e == hipSuccess ? MS_OK : MS_ERR_HIP;
+}
+
+ms_status ms_batched_status(const void* d_ws, void* stream) {
+  if (!d_ws) return MS_ERR_INVALID_ARG;
+  uint32_t ctl[2] = {0, 0};
+  hipStream_t st = (hipStream_t)stream;
+  if (hipMemcpyAsync(ctl, d_ws, sizeof(ctl), hipMemcpyDeviceToHost, st) != hipSuccess)
+    return MS_ERR_HIP;
+  if (hipStreamSynchronize(st) != hipSuccess) return MS_ERR_HIP;
+  return ctl[1] ? MS_ERR_TIMEOUT : MS_OK;
 }
 
 ms_status ms_learned_fit(const uint32_t* d_sample, size_t n_sample, const uint32_t* d_splitters,
@@ -416,6 +547,86 @@ ms_status ms_learned_fit(const uint32_t* d_sample, size_t n_sample, const uint32
   hipLaunchKernelGGL(ms::fit_leaf_kernel, dim3(ms::kLeaves), B, 0, st, p);
   hipLaunchKernelGGL(ms::fit_fill_empty_kernel, dim3(1), dim3(64), 0, st, p);
   return hipGetLastError() == hipSuccess ? MS_OK : MS_ERR_HIP;
+}
+
+ms_status ms_autotune(int op, const uint32_t* d_keys_in, const uint32_t* d_vals_in,
+                      uint32_t* d_keys_out, uint32_t* d_vals_out, const uint64_t* d_seg,
+                      uint32_t num_inst, size_t n, uint32_t m, const ms_bucket_fn* fn,
+                      void* d_ws, size_t ws_bytes, int reps, const ms_options* base,
+                      ms_options* best, float* best_ms, void* stream) {
+  if (!best || reps < 1 || reps > 1000) return MS_ERR_INVALID_ARG;
+  struct Cand { int reorder, wpb, nw; uint32_t claim; };
+  static const Cand kMulti[] = {{MS_REORDER_BLOCK, 8, 8, 0},  {MS_REORDER_BLOCK, 8, 4, 0},
+                                {MS_REORDER_BLOCK, 4, 8, 0},  {MS_REORDER_BLOCK, 4, 16, 0},
+                                {MS_REORDER_WAVE, 8, 8, 0},   {MS_REORDER_WAVE, 4, 16, 0},
+                                {MS_REORDER_NONE, 8, 8, 0}};
+  static const Cand kBatch[] = {{MS_REORDER_BLOCK, 8, 8, 1},  {MS_REORDER_BLOCK, 8, 8, 4},
+                                {MS_REORDER_BLOCK, 8, 8, 8},  {MS_REORDER_BLOCK, 8, 8, 16},
+                                {MS_REORDER_BLOCK, 8, 8, 32}, {MS_REORDER_BLOCK, 8, 4, 4},
+                                {MS_REORDER_BLOCK, 8, 4, 16}, {MS_REORDER_BLOCK, 8, 4, 32}};
+  const bool batched = op == MS_OP_BATCHED;
+  const bool radix = op == MS_OP_RADIX_SORT || op == MS_OP_RADIX_SORT_PAIRS;
+  if (!batched && !radix && op != MS_OP_KEYS && op != MS_OP_PAIRS) return MS_ERR_INVALID_ARG;
+  const Cand* cands = batched ? kBatch : kMulti;
+  const int ncand = batched ? (int)(sizeof(kBatch) / sizeof(Cand)) : (int)(sizeof(kMulti) / sizeof(Cand));
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return MS_ERR_HIP;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    return MS_ERR_HIP;
+  }
+  ms_status result = MS_ERR_UNSUPPORTED;
+  float best_t = 0.0f;
+  for (int c = 0; c < ncand; ++c) {
+    ms_options o;
+    memset(&o, 0, sizeof(o));
+    if (base) o = *base;
+    o.stage_events = nullptr;
+    o.reorder = cands[c].reorder;
+    o.waves_per_block = cands[c].wpb;
+    o.items_per_lane = cands[c].nw;
+    if (batched) o.batch_claim = cands[c].claim;
+    int wop = batched ? MS_OP_BATCHED
+                      : radix ? (d_vals_in ? MS_OP_RADIX_SORT_PAIRS : MS_OP_RADIX_SORT)
+                              : (d_vals_in ? MS_OP_PAIRS : MS_OP_KEYS);
+    size_t need = ms_workspace_size(wop, n, radix ? 256 : m, num_inst, &o);
+    if (need == 0 || need > ws_bytes) continue;
+    auto run = [&]() -> ms_status {
+      if (batched)
+        return ms_batched(d_keys_in, d_vals_in, d_keys_out, d_vals_out, d_seg, num_inst, n, m, fn,
+                          nullptr, d_ws, ws_bytes, &o, stream);
+      if (radix)
+        return ms_radix_sort(d_keys_in, d_vals_in, d_keys_out, d_vals_out, n, m, d_ws, ws_bytes,
+                             &o, stream);
+      return ms_pairs(d_keys_in, d_vals_in, d_keys_out, d_vals_out, nullptr, n, m, fn, d_ws,
+                      ws_bytes, &o, stream);
+    };
+    ms_status rc = run();
+    if (rc != MS_OK) {
+      result = rc;
+      break;
+    }
+    hipEventRecord(e0, st);
+    for (int r = 0; r < reps && rc == MS_OK; ++r) rc = run();
+    hipEventRecord(e1, st);
+    if (rc != MS_OK || hipEventSynchronize(e1) != hipSuccess) {
+      result = rc != MS_OK ? rc : MS_ERR_HIP;
+      break;
+    }
+    float t = 0.0f;
+    hipEventElapsedTime(&t, e0, e1);
+    t /= (float)reps;
+    if (result != MS_OK || t < best_t) {
+      best_t = t;
+      *best = o;
+      result = MS_OK;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (result == MS_OK && best_ms) *best_ms = best_t;
+  return result;
 }
 
 ms_status ms_copy_u32(uint32_t* d_dst, const uint32_t* d_src, size_t n, void* stream) {
