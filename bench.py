@@ -391,7 +391,7 @@ def main():
     radix = kind.startswith("radix")
     op = (ms.OP_RADIX_SORT_PAIRS if kv else ms.OP_RADIX_SORT) if radix else \
         (ms.OP_PAIRS if kv else ms.OP_KEYS)
-    ws = torch.empty(max(256, ms.workspace_size(op, n, m, 0, opt)), dtype=torch.uint8,
+    ws = torch.empty(max(256, ms.workspace_size(op, n, 256 if radix else m, 0, opt)), dtype=torch.uint8,
                      device=dev)
     fn = ms.BucketFn.shift_mask(shift, m - 1)
 

@@ -163,8 +163,9 @@ enum {
 /*
  * Bytes of workspace an operation needs.  n = elements (for MS_OP_BATCHED the
  * total over all instances, for MS_OP_LEARNED_FIT the sample size), m =
- * buckets, num_inst = instances (MS_OP_BATCHED only), opt as passed to the
- * call (NULL = defaults).  Returns 0 only for arguments that are invalid.
+ * buckets (for the radix sort: 2^bits_per_pass), num_inst = instances
+ * (MS_OP_BATCHED only), opt as passed to the call (NULL = defaults).  Returns
+ * 0 only for arguments that are invalid.
  */
 size_t ms_workspace_size(int op, size_t n, uint32_t m, uint32_t num_inst,
                          const ms_options* opt);

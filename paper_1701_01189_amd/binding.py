@@ -243,8 +243,8 @@ def radix_sort(keys_in, vals_in=None, bits_per_pass=8, keys_out=None, vals_out=N
         keys_out = torch.empty_like(keys_in)
     if kv and vals_out is None:
         vals_out = torch.empty_like(vals_in)
-    w, wb = _workspace(OP_RADIX_SORT_PAIRS if kv else OP_RADIX_SORT, n, 256, keys_in.device,
-                       options, ws=ws)
+    w, wb = _workspace(OP_RADIX_SORT_PAIRS if kv else OP_RADIX_SORT, n, 1 << bits_per_pass,
+                       keys_in.device, options, ws=ws)
     o = options.c() if options is not None else None
     rc = lib().ms_radix_sort(_u32(keys_in, "keys_in"), _u32(vals_in, "vals_in"),
                              _u32(keys_out, "keys_out"), _u32(vals_out, "vals_out"), n,
@@ -296,7 +296,7 @@ def autotune(op, keys_in, vals_in, m, fn=None, seg=None, reps=3, base=None, stre
                           (8, 8, 3)):
         if op == OP_BATCHED and (wpb != 8 or mode != 1):
             continue
-        need = max(need, workspace_size(op, n, 256 if radix else m, num,
+        need = max(need, workspace_size(op, n, (1 << m) if radix else m, num,
                                         Options(reorder=mode, waves_per_block=wpb,
                                                 items_per_lane=nw)))
     ws = torch.empty(max(need, 256), dtype=torch.uint8, device=keys_in.device)
