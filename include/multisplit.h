@@ -137,6 +137,7 @@ enum {
  *                    instance's ready flag before giving up (0 = 2^22).
  *   test_flags       bit 0: ms_batched never raises ready flags, so every
  *                    wait expires (exercises the timeout path; for tests).
+ *   prescan          MS_PRESCAN_*: how the pre-scan counts buckets.
  */
 typedef struct {
   int32_t reorder;
@@ -148,7 +149,24 @@ typedef struct {
   uint32_t batch_claim;
   uint32_t spin_limit;
   uint32_t test_flags;
+  int32_t prescan;
 } ms_options;
+
+/*
+ * Pre-scan histogram method (both give the same H):
+ *   MS_PRESCAN_BALLOT  Algorithm 2's window histogram from ballots (Section
+ *                      5.5.1; Section 5.7 for m > 64).
+ *   MS_PRESCAN_LANES   per-(bucket, lane) LDS counters incremented by LDS
+ *                      atomics; cost independent of m and of skew.  Block
+ *                      reordering only (MS_ERR_UNSUPPORTED otherwise).
+ *   MS_PRESCAN_AUTO    LANES with block reordering, BALLOT otherwise.
+ * ms_batched always counts with ballots.
+ */
+enum {
+  MS_PRESCAN_AUTO = 0,
+  MS_PRESCAN_BALLOT = 1,
+  MS_PRESCAN_LANES = 2
+};
 
 /* Operations for ms_workspace_size(). */
 enum {

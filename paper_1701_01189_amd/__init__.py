@@ -9,6 +9,7 @@ generators (``inputs``).  The native library is loaded on first use.
 """
 from .binding import (BUCKET_DIV, BUCKET_LEARNED, BUCKET_SHIFT_MASK, BUCKET_SPLITTERS,
                       MODEL_FLOATS, OP_BATCHED, OP_KEYS, OP_LEARNED_FIT, OP_PAIRS, OP_RADIX_SORT, OP_RADIX_SORT_PAIRS,
+                      PRESCAN_AUTO, PRESCAN_BALLOT, PRESCAN_LANES,
                       REORDER_AUTO, REORDER_BLOCK, REORDER_NONE, REORDER_WAVE, BucketFn,
                       MultisplitError, Options, batched, batched_status, copy_u32, keys, learned_fit, pairs, radix_sort,
                       workspace_size)

@@ -19,6 +19,7 @@ STATUS = {0: "MS_OK", -1: "MS_ERR_INVALID_ARG", -2: "MS_ERR_WORKSPACE", -3: "MS_
 
 BUCKET_SHIFT_MASK, BUCKET_DIV, BUCKET_SPLITTERS, BUCKET_LEARNED = 0, 1, 2, 3
 REORDER_AUTO, REORDER_BLOCK, REORDER_WAVE, REORDER_NONE = 0, 1, 2, 3
+PRESCAN_AUTO, PRESCAN_BALLOT, PRESCAN_LANES = 0, 1, 2
 OP_KEYS, OP_PAIRS, OP_BATCHED, OP_RADIX_SORT, OP_RADIX_SORT_PAIRS, OP_LEARNED_FIT = range(6)
 MODEL_LEAVES = 256
 MODEL_FLOATS = 2 + 2 * MODEL_LEAVES
@@ -41,7 +42,7 @@ class OptionsC(ctypes.Structure):
                 ("items_per_lane", ctypes.c_int32), ("max_chunks", ctypes.c_int32),
                 ("stage_events", ctypes.c_void_p), ("d_mispredicts", ctypes.c_void_p),
                 ("batch_claim", ctypes.c_uint32), ("spin_limit", ctypes.c_uint32),
-                ("test_flags", ctypes.c_uint32)]
+                ("test_flags", ctypes.c_uint32), ("prescan", ctypes.c_int32)]
 
 
 _lib = None
@@ -155,8 +156,9 @@ class Options:
 
     def __init__(self, reorder=0, waves_per_block=0, items_per_lane=0, max_chunks=0,
                  stage_events=None, mispredicts=None, batch_claim=0, spin_limit=0,
-                 test_flags=0):
+                 test_flags=0, prescan=0):
         self.reorder, self.waves_per_block = reorder, waves_per_block
+        self.prescan = prescan
         self.items_per_lane, self.max_chunks = items_per_lane, max_chunks
         self.batch_claim, self.spin_limit, self.test_flags = batch_claim, spin_limit, test_flags
         self.stage_events = stage_events   # list of 4 torch.cuda.Event or None
@@ -170,7 +172,7 @@ class Options:
             ev = ctypes.cast(self._ev, ctypes.c_void_p)
         return OptionsC(self.reorder, self.waves_per_block, self.items_per_lane,
                         self.max_chunks, ev, _ptr(self.mispredicts), self.batch_claim,
-                        self.spin_limit, self.test_flags)
+                        self.spin_limit, self.test_flags, self.prescan)
 
 
 def _opt(options):
@@ -313,7 +315,7 @@ def autotune(op, keys_in, vals_in, m, fn=None, seg=None, reps=3, base=None, stre
     opt = Options(reorder=best.reorder, waves_per_block=best.waves_per_block,
                   items_per_lane=best.items_per_lane, max_chunks=best.max_chunks,
                   batch_claim=best.batch_claim, spin_limit=best.spin_limit,
-                  test_flags=best.test_flags)
+                  test_flags=best.test_flags, prescan=best.prescan)
     return opt, float(ms_.value)
 
 

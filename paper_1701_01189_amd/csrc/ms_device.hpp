@@ -71,7 +71,10 @@ __device__ __forceinline__ uint64_t match_bucket(uint32_t b, uint64_t valid_mask
   uint32_t lo = (uint32_t)valid_mask, hi = (uint32_t)(valid_mask >> 32);
 #pragma unroll
   for (int k = 0; k < BITS; ++k) {
-    const uint32_t sel = bit_spread(b, k);
+    uint32_t sel = bit_spread(b, k);
+    // Opaque to the optimiser, so the ballot compares `sel` itself instead
+    // of re-deriving the bit with an extra shift.
+    asm("" : "+v"(sel));
     const uint64_t bal = ballot(sel != 0u);
     lo = and_agree(lo, (uint32_t)bal, sel);
     hi = and_agree(hi, (uint32_t)(bal >> 32), sel);

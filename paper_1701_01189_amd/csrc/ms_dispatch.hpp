@@ -16,6 +16,7 @@ struct PreArgs {
   BucketParams bp;
   uint32_t* H;
   int mode;
+  int hist;  // kHistBallot / kHistLanes (block mode only)
   hipStream_t stream;
 };
 
@@ -49,11 +50,16 @@ constexpr int kPreWaves = 8;
 
 template <int Kind, int BITS>
 hipError_t pre_launch(const PreArgs& a) {
-  if (a.mode == kBlock) {
-    hipLaunchKernelGGL((prescan_kernel<Kind, BITS, kPreWaves, kPreWaves>), dim3(a.plan.L0),
-                       dim3(kPreWaves * kWave), 0, a.stream, a.keys, a.plan, a.bp, a.H);
+  if (a.mode == kBlock && a.hist == kHistLanes) {
+    hipLaunchKernelGGL((prescan_kernel<Kind, BITS, kPreWaves, kPreWaves, kHistLanes>),
+                       dim3(a.plan.L0), dim3(kPreWaves * kWave), 0, a.stream, a.keys, a.plan,
+                       a.bp, a.H);
+  } else if (a.mode == kBlock) {
+    hipLaunchKernelGGL((prescan_kernel<Kind, BITS, kPreWaves, kPreWaves, kHistBallot>),
+                       dim3(a.plan.L0), dim3(kPreWaves * kWave), 0, a.stream, a.keys, a.plan,
+                       a.bp, a.H);
   } else {
-    hipLaunchKernelGGL((prescan_kernel<Kind, BITS, kPreWaves, 1>),
+    hipLaunchKernelGGL((prescan_kernel<Kind, BITS, kPreWaves, 1, kHistBallot>),
                        dim3((a.plan.L0 + kPreWaves - 1) / kPreWaves), dim3(kPreWaves * kWave), 0,
                        a.stream, a.keys, a.plan, a.bp, a.H);
   }

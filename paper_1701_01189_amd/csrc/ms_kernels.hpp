@@ -67,23 +67,45 @@ __device__ __forceinline__ uint32_t group_exclusive_scan(uint32_t v, uint32_t* t
 }
 
 // ---------------------------------------------------------------------------
-// Pre-scan: one column of H per chunk (Algorithm 1's pre-scan with the
-// window histogram of Algorithm 2).  WPG wavefronts share a chunk; a
-// workgroup of WPB wavefronts serves WPB / WPG chunks.  Order inside a chunk
-// does not matter for a histogram, so wavefronts stride over its windows.
-// H is bucket-major: H[b * L0 + c].
+// Pre-scan: one column of H per chunk (Algorithm 1's pre-scan).  WPG
+// wavefronts share a chunk; a workgroup of WPB wavefronts serves WPB / WPG
+// chunks.  Order inside a chunk does not matter for a histogram, so
+// wavefronts stride over its windows.  H is bucket-major: H[b * L0 + c].
+//
+// Two ways to count, same result:
+//  kHistBallot  the window histogram of Algorithm 2 (ballots, counts in
+//               registers; about 4 VALU per vote bit per window);
+//  kHistLanes   one LDS counter per (bucket, lane) shared by the workgroup's
+//               wavefronts: every element adds 1 to its lane's counter of its
+//               bucket with an LDS atomic.  The 64 lanes of an instruction
+//               always hit 64 distinct counters in 64 distinct banks, so
+//               neither skew nor m changes its cost (one address VALU per
+//               window besides the bucket id).
+//               Workgroup-shared chunks only (WPG > 1).
 // ---------------------------------------------------------------------------
-template <int Kind, int BITS, int WPB, int WPG>
+enum Hist { kHistBallot = 0, kHistLanes = 1 };
+
+template <int Kind, int BITS, int WPB, int WPG, int HIST>
 __global__ void __launch_bounds__(WPB* kWave)
 prescan_kernel(const uint32_t* __restrict__ keys, Plan plan, BucketParams bp,
                uint32_t* __restrict__ H) {
+  static_assert(HIST == kHistBallot || WPG > 1, "lane counters need a shared chunk");
   constexpr int GPB = WPB / WPG;
   constexpr int MB = Owned<BITS>::value;
   constexpr int U = 16;  // windows in flight per wavefront
+  constexpr bool LANES = (HIST == kHistLanes);
+  constexpr int NB = 1 << BITS;  // counter rows of kHistLanes
   __shared__ BucketLds tables;
-  __shared__ uint32_t s_hist[(WPG > 1) ? WPB * kMaxBuckets : 1];
+  __shared__ uint32_t s_hist[(WPG > 1 && !LANES) ? WPB * kMaxBuckets : 1];
+  __shared__ uint32_t s_lane[LANES ? NB * kWave : 1];  // [bucket][lane]
+  if (LANES)
+    for (uint32_t i = threadIdx.x; i < NB * kWave; i += WPB * kWave) s_lane[i] = 0u;
   stage_bucket_tables<Kind>(bp, &tables);
   __syncthreads();
+  auto lane_count = [&](uint32_t b, uint32_t lane) {
+    __hip_atomic_fetch_add(&s_lane[b * kWave + lane], 1u, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
+  };
   Bucket<Kind, BITS> bf(bp, &tables);
 
   const uint32_t lane = lane_id();
@@ -122,8 +144,12 @@ prescan_kernel(const uint32_t* __restrict__ keys, Plan plan, BucketParams bp,
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        window_histogram<BITS>(b[u], ~0ull, ls, cnt);
-        __builtin_amdgcn_sched_barrier(0);
+        if (LANES) {
+          lane_count(b[u], lane);
+        } else {
+          window_histogram<BITS>(b[u], ~0ull, ls, cnt);
+          __builtin_amdgcn_sched_barrier(0);
+        }
       }
       gi = next;
     }
@@ -134,7 +160,11 @@ prescan_kernel(const uint32_t* __restrict__ keys, Plan plan, BucketParams bp,
       for (int u = 0; u < U; ++u) {
         const bool valid = (uint32_t)(u * kWave) + lane < rem;
         const uint32_t b = valid ? bf(p[u * kWave]) : 0u;
-        window_histogram<BITS>(b, ballot(valid), ls, cnt);
+        if (LANES) {
+          if (valid) lane_count(b, lane);
+        } else {
+          window_histogram<BITS>(b, ballot(valid), ls, cnt);
+        }
       }
     }
   }
@@ -144,6 +174,15 @@ prescan_kernel(const uint32_t* __restrict__ keys, Plan plan, BucketParams bp,
       for (int t = 0; t < MB; ++t) {
         uint32_t b = lane + kWave * t;
         if (b < plan.m) H[b * plan.L0 + c] = cnt[t];
+      }
+    }
+  } else if (LANES) {
+    // column total of bucket b = sum of its 64 lane counters
+    __syncthreads();
+    if (c < plan.L0) {
+      for (uint32_t b = w; b < plan.m; b += WPB) {
+        const uint32_t s = wave_inclusive_scan(s_lane[b * kWave + lane], lane);
+        if (lane == kWave - 1) H[b * plan.L0 + c] = s;
       }
     }
   } else {
@@ -211,7 +250,11 @@ __device__ __forceinline__ void tile_rank_reorder_write(const BF& bf, uint32_t (
     const uint32_t r = count_below(mm), cnt = popc64(mm);
     const uint32_t before = lds_get(c.my_cnt + bk[j]);
     lr[j] = before + r;
-    if (valid && r + 1 == cnt) lds_put(c.my_cnt + bk[j], before + cnt);
+    // Every lane of a bucket read the same `before` and holds the same
+    // count, so all of them store the same new value (no branch).  An
+    // invalid lane carries bucket 0 and counts the valid bucket-0 lanes, so
+    // it stores that same value too.
+    lds_put(c.my_cnt + bk[j], before + cnt);
     wave_order();
   }
   group_sync<WPG>();
@@ -377,7 +420,7 @@ postscan_kernel(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict
         const uint64_t mm = match_bucket<BITS>(b, ballot(valid));
         const uint32_t r = count_below(mm), cnt = popc64(mm);
         const uint32_t pos = lds_get(my_cnt + b);
-        if (valid && r + 1 == cnt) lds_put(my_cnt + b, pos + cnt);
+        lds_put(my_cnt + b, pos + cnt);  // same value from every lane of b
         wave_order();
         const uint32_t o = pos + r;
         if (valid && o < plan.n) {

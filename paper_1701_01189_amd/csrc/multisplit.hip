@@ -9,7 +9,7 @@
 #include <stdint.h>
 #include <string.h>
 
-#include "../../include/multisplit.h"
+#include "multisplit.h"
 #include "ms_aux_kernels.hpp"
 #include "ms_learned.hpp"
 #include "ms_dispatch.hpp"
@@ -28,6 +28,7 @@ struct Shape {
   int wpb;      // wavefronts per workgroup
   int nw;       // windows per wavefront per tile
   uint32_t max_chunks;
+  int hist;     // pre-scan histogram: ms::kHistBallot / kHistLanes
 };
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -49,6 +50,7 @@ int resolve_shape(const ms_options* opt, uint32_t m, Shape* s) {
   s->wpb = m <= 64 ? 4 : 8;
   s->nw = 8;
   s->max_chunks = 0;
+  int prescan = MS_PRESCAN_AUTO;
   if (opt) {
     if (opt->reorder < 0 || opt->reorder > MS_REORDER_NONE) return MS_ERR_INVALID_ARG;
     if (opt->reorder == MS_REORDER_BLOCK) s->mode = ms::kBlock;
@@ -58,7 +60,13 @@ int resolve_shape(const ms_options* opt, uint32_t m, Shape* s) {
     if (opt->items_per_lane) s->nw = opt->items_per_lane;
     if (opt->max_chunks < 0) return MS_ERR_INVALID_ARG;
     s->max_chunks = (uint32_t)opt->max_chunks;
+    if (opt->prescan < MS_PRESCAN_AUTO || opt->prescan > MS_PRESCAN_LANES) return MS_ERR_INVALID_ARG;
+    prescan = opt->prescan;
   }
+  // Lane counters need a chunk shared by a workgroup (block reordering).
+  if (prescan == MS_PRESCAN_LANES && s->mode != ms::kBlock) return MS_ERR_UNSUPPORTED;
+  s->hist = (prescan == MS_PRESCAN_BALLOT || s->mode != ms::kBlock) ? ms::kHistBallot
+                                                                     : ms::kHistLanes;
   return shape_supported(*s) ? MS_OK : MS_ERR_UNSUPPORTED;
 }
 
@@ -295,7 +303,7 @@ ms_status run_multisplit(const uint32_t* ki, const uint32_t* vi, uint32_t* ko, u
   BucketParams bp = make_params(fn, m, opt ? opt->d_mispredicts : nullptr);
   const int bits = (int)ceil_log2(m);
   if (record(opt, 0, st) != hipSuccess) return MS_ERR_HIP;
-  ms::PreArgs pa{ki, p, bp, w.H, s.mode, st};
+  ms::PreArgs pa{ki, p, bp, w.H, s.mode, s.hist, st};
   if (pre_by_kind(fn->kind, pa, bits) != hipSuccess) return MS_ERR_HIP;
   if (record(opt, 1, st) != hipSuccess) return MS_ERR_HIP;
   hipLaunchKernelGGL(ms::scan_rows_kernel, dim3(m), dim3(ms::kScanThreads), 0, st, w.H, p.L0,
@@ -591,6 +599,7 @@ ms_status ms_autotune(int op, const uint32_t* d_keys_in, const uint32_t* d_vals_
     o.waves_per_block = cands[c].wpb;
     o.items_per_lane = cands[c].nw;
     if (batched) o.batch_claim = cands[c].claim;
+    if (o.prescan == MS_PRESCAN_LANES && o.reorder != MS_REORDER_BLOCK) o.prescan = MS_PRESCAN_AUTO;
     int wop = batched ? MS_OP_BATCHED
                       : radix ? (d_vals_in ? MS_OP_RADIX_SORT_PAIRS : MS_OP_RADIX_SORT)
                               : (d_vals_in ? MS_OP_PAIRS : MS_OP_KEYS);

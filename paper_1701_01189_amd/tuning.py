@@ -33,10 +33,12 @@ def tuned_options(op, keys_in, vals_in, m, fn=None, seg=None, cache=None, reps=3
     if not retune and key in table:
         e = table[key]
         return ms.Options(reorder=e["reorder"], waves_per_block=e["waves_per_block"],
-                          items_per_lane=e["items_per_lane"], batch_claim=e["batch_claim"]), e
+                          items_per_lane=e["items_per_lane"], batch_claim=e["batch_claim"],
+                          prescan=e.get("prescan", 0)), e
     opt, t = ms.autotune(op, keys_in, vals_in, m, fn=fn, seg=seg, reps=reps)
     e = {"reorder": opt.reorder, "waves_per_block": opt.waves_per_block,
-         "items_per_lane": opt.items_per_lane, "batch_claim": opt.batch_claim, "ms": t}
+         "items_per_lane": opt.items_per_lane, "batch_claim": opt.batch_claim,
+         "prescan": opt.prescan, "ms": t}
     table[key] = e
     d = os.path.dirname(path)
     if d:

@@ -74,6 +74,11 @@ def test_host_validation_rejects_before_launch(L):
     assert L.ms_keys(ki, ko, None, n, 32, ctypes.byref(fn), ws, need, ctypes.byref(o), None) == -6
     o = OptionsC(9, 0, 0, 0, None, None)
     assert L.ms_keys(ki, ko, None, n, 32, ctypes.byref(fn), ws, need, ctypes.byref(o), None) == -1
+    # pre-scan method: out of range, and lane counters without block reordering
+    o = OptionsC(0, 0, 0, 0, None, None, 0, 0, 0, 3)
+    assert L.ms_keys(ki, ko, None, n, 32, ctypes.byref(fn), ws, need, ctypes.byref(o), None) == -1
+    o = OptionsC(2, 8, 8, 0, None, None, 0, 0, 0, 2)
+    assert L.ms_keys(ki, ko, None, n, 32, ctypes.byref(fn), ws, need, ctypes.byref(o), None) == -6
     # pairs: values missing on one side
     assert L.ms_pairs(ki, None, ko, fake(0x30000000), None, n, 32, ctypes.byref(fn), ws, need,
                       None, None) == -1

@@ -52,7 +52,7 @@ def fn_for(kind, m, seed=0):
     return ms.BucketFn.splitter(t), dict(splitters=spl[:m - 1]), oracle.SPLITTERS, t
 
 
-def check_case(n, m, kind, kv, shape, seed):
+def check_case(n, m, kind, kv, shape, seed, prescan=0):
     from paper_1701_01189_amd import binding as ms
     if kind == "shift" and m & (m - 1):
         return
@@ -62,8 +62,10 @@ def check_case(n, m, kind, kv, shape, seed):
     vals = inputs.index_values(n)
     fn, okw, okind, _keep = fn_for(kind, m, seed)
     ek, ev, eo = oracle.multisplit(keys, m, okind, vals=vals if kv else None, **okw)
-    opt = ms.Options(reorder=shape[0], waves_per_block=shape[1], items_per_lane=shape[2])
-    say("case n=%d m=%d kind=%s kv=%d shape=%s seed=%d" % (n, m, kind, kv, shape, seed))
+    opt = ms.Options(reorder=shape[0], waves_per_block=shape[1], items_per_lane=shape[2],
+                     prescan=prescan)
+    say("case n=%d m=%d kind=%s kv=%d shape=%s seed=%d prescan=%d" % (n, m, kind, kv, shape,
+                                                                      seed, prescan))
     if kv:
         k, v, o = ms.pairs(dev(keys), dev(vals), m, fn, options=opt)
         torch.cuda.synchronize()
@@ -82,6 +84,33 @@ def test_small_shapes_ragged(shape):
     for i, (n, m) in enumerate(combos):
         for kind in ("shift", "div", "splitters"):
             check_case(n, m, kind, kv=(i % 2 == 0), shape=shape, seed=11 * i + 3)
+
+
+@pytest.mark.parametrize("prescan", [1, 2])  # ballot histogram, lane counters
+def test_prescan_methods(prescan):
+    """Both pre-scan histograms under block reordering, every bucket kind."""
+    combos = [(1, 1), (65, 3), (4097, 33), (30001, 128), (100003, 200), (262147, 256),
+              (524309, 32), (70001, 64)]
+    for i, (n, m) in enumerate(combos):
+        for kind in ("shift", "div", "splitters"):
+            for shape in ((1, 8, 8), (1, 4, 8)):
+                check_case(n, m, kind, kv=(i % 2 == 1), shape=shape, seed=5 * i + 1,
+                           prescan=prescan)
+
+
+@pytest.mark.parametrize("prescan", [1, 2])
+def test_prescan_methods_one_bucket(prescan):
+    """Every key in one bucket (the worst case for same-address LDS traffic)."""
+    from paper_1701_01189_amd import binding as ms
+    n = 200_003
+    keys = inputs.uniform_u32(19, n) & np.uint32(0x00FFFFFF) | np.uint32(0x7B000000)
+    for m, shift in ((256, 24), (32, 27), (2, 31)):
+        ek, _, eo = oracle.multisplit(keys, m, oracle.SHIFT_MASK, shift=shift, mask=m - 1)
+        say("case one-bucket prescan=%d m=%d" % (prescan, m))
+        k, o = ms.keys(dev(keys), m, ms.BucketFn.shift_mask(shift, m - 1),
+                       options=ms.Options(reorder=1, prescan=prescan))
+        np.testing.assert_array_equal(host(k), ek)
+        np.testing.assert_array_equal(host(o), eo)
 
 
 @pytest.mark.parametrize("shape", SHAPES)
