@@ -585,7 +585,7 @@ ms_status ms_autotune(int op, const uint32_t* d_keys_in, const uint32_t* d_vals_
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return MS_ERR_HIP;
   if (hipEventCreate(&e1) != hipSuccess) {
-    hipEventDestroy(e0);
+    (void)hipEventDestroy(e0);
     return MS_ERR_HIP;
   }
   ms_status result = MS_ERR_UNSUPPORTED;
@@ -620,15 +620,21 @@ ms_status ms_autotune(int op, const uint32_t* d_keys_in, const uint32_t* d_vals_
       result = rc;
       break;
     }
-    hipEventRecord(e0, st);
+    if (hipEventRecord(e0, st) != hipSuccess) {
+      result = MS_ERR_HIP;
+      break;
+    }
     for (int r = 0; r < reps && rc == MS_OK; ++r) rc = run();
-    hipEventRecord(e1, st);
-    if (rc != MS_OK || hipEventSynchronize(e1) != hipSuccess) {
+    if (rc != MS_OK || hipEventRecord(e1, st) != hipSuccess ||
+        hipEventSynchronize(e1) != hipSuccess) {
       result = rc != MS_OK ? rc : MS_ERR_HIP;
       break;
     }
     float t = 0.0f;
-    hipEventElapsedTime(&t, e0, e1);
+    if (hipEventElapsedTime(&t, e0, e1) != hipSuccess) {
+      result = MS_ERR_HIP;
+      break;
+    }
     t /= (float)reps;
     if (result != MS_OK || t < best_t) {
       best_t = t;
@@ -636,8 +642,8 @@ ms_status ms_autotune(int op, const uint32_t* d_keys_in, const uint32_t* d_vals_
       result = MS_OK;
     }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (result == MS_OK && best_ms) *best_ms = best_t;
   return result;
 }
