@@ -41,14 +41,15 @@ uint32_t ceil_log2(uint32_t m) {
 
 bool shape_supported(const Shape& s) { return ms::post_shape_supported(s.mode, s.wpb, s.nw); }
 
-// Default: block-level reordering (BMS) with 8 windows per wavefront, 4
-// wavefronts per workgroup for m <= 64 and 8 above (measured fastest on
-// MI355X for 2^25 pairs and 2^28 keys); the paper's own defaults are 8 warps
-// x 4 windows of 32 (Section 6, "Parameters").
+// Default: block-level reordering (BMS); 4 wavefronts x 16 windows per tile
+// for m <= 64, 8 x 8 above (measured fastest on MI355X for 2^25 pairs and
+// 2^28 keys: longer bucket runs per tile mean fewer partial cache lines);
+// the paper's own defaults are 8 warps x 4 windows of 32 (Section 6,
+// "Parameters").
 int resolve_shape(const ms_options* opt, uint32_t m, Shape* s) {
   s->mode = ms::kBlock;
   s->wpb = m <= 64 ? 4 : 8;
-  s->nw = 8;
+  s->nw = m <= 64 ? 16 : 8;
   s->max_chunks = 0;
   int prescan = MS_PRESCAN_AUTO;
   if (opt) {

@@ -93,7 +93,7 @@ def test_prescan_methods(prescan):
               (524309, 32), (70001, 64)]
     for i, (n, m) in enumerate(combos):
         for kind in ("shift", "div", "splitters"):
-            for shape in ((1, 8, 8), (1, 4, 8)):
+            for shape in ((1, 8, 8), (1, 4, 8), (1, 4, 16)):
                 check_case(n, m, kind, kv=(i % 2 == 1), shape=shape, seed=5 * i + 1,
                            prescan=prescan)
 
