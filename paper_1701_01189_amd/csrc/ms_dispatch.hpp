@@ -38,7 +38,8 @@ struct PostArgs {
 // Shapes with an instantiated post-scan: (mode, waves per block, windows).
 inline bool post_shape_supported(int mode, int wpb, int nw) {
   if (mode == kBlock)
-    return (wpb == 8 && (nw == 4 || nw == 8)) || (wpb == 4 && (nw == 8 || nw == 16));
+    return (wpb == 8 && (nw == 4 || nw == 8)) || (wpb == 4 && (nw == 8 || nw == 16)) ||
+           (wpb == 16 && nw == 8);
   if (mode == kWaveMode) return (wpb == 8 && nw == 8) || (wpb == 4 && nw == 16);
   if (mode == kDirect) return wpb == 8 && nw == 8;
   return false;
@@ -98,6 +99,7 @@ hipError_t post_shape(const PostArgs& a) {
   if (a.mode == kBlock) {
     if (a.wpb == 8 && a.nw == 8) return post_launch<Kind, BITS, KV, 8, 8, kBlock>(a);
     if (a.wpb == 8 && a.nw == 4) return post_launch<Kind, BITS, KV, 8, 4, kBlock>(a);
+    if (a.wpb == 16 && a.nw == 8) return post_launch<Kind, BITS, KV, 16, 8, kBlock>(a);
     if (a.wpb == 4 && a.nw == 8) return post_launch<Kind, BITS, KV, 4, 8, kBlock>(a);
     if (a.wpb == 4 && a.nw == 16) return post_launch<Kind, BITS, KV, 4, 16, kBlock>(a);
   } else if (a.mode == kWaveMode) {

@@ -41,14 +41,19 @@ uint32_t ceil_log2(uint32_t m) {
 
 bool shape_supported(const Shape& s) { return ms::post_shape_supported(s.mode, s.wpb, s.nw); }
 
-// Default: block-level reordering (BMS); 4 wavefronts x 16 windows per tile
-// for m <= 64, 8 x 8 above (measured fastest on MI355X for 2^25 pairs and
-// 2^28 keys: longer bucket runs per tile mean fewer partial cache lines);
-// the paper's own defaults are 8 warps x 4 windows of 32 (Section 6,
-// "Parameters").
-int resolve_shape(const ms_options* opt, uint32_t m, Shape* s) {
+// Default: block-level reordering (BMS) with tiles sized so that bucket
+// runs stay long (fewer partial cache lines at run ends, which L2 must merge
+// with the next tile's writes): 4 wavefronts x 16 windows for m <= 64;
+// above, 16 x 8 (8192 elements) for bucket functions computed in registers
+// and 8 x 8 for those that search LDS tables (their extra registers make
+// the larger tile slower).  Measured on MI355X with 2^25 pairs, 2^28 keys,
+// 2^28-pair radix sort and 2^27 range keys.  The paper's own defaults are 8
+// warps x 4 windows of 32 (Section 6, "Parameters").  `kind` < 0: unknown
+// (the workspace query takes the larger of the two plans).
+int resolve_shape(const ms_options* opt, uint32_t m, int kind, Shape* s) {
+  const bool table_kind = kind == MS_BUCKET_SPLITTERS || kind == MS_BUCKET_LEARNED;
   s->mode = ms::kBlock;
-  s->wpb = m <= 64 ? 4 : 8;
+  s->wpb = m <= 64 ? 4 : (table_kind ? 8 : 16);
   s->nw = m <= 64 ? 16 : 8;
   s->max_chunks = 0;
   int prescan = MS_PRESCAN_AUTO;
@@ -357,13 +362,18 @@ const char* ms_version(void) { return "multisplit-gfx950 0.1"; }
 
 size_t ms_workspace_size(int op, size_t n, uint32_t m, uint32_t num_inst, const ms_options* opt) {
   (void)num_inst;
-  Shape s;
-  if (resolve_shape(opt, m, &s) != MS_OK) return 0;
+  Shape s;  // radix passes use shift/mask buckets
+  if (resolve_shape(opt, m, MS_BUCKET_SHIFT_MASK, &s) != MS_OK) return 0;
   switch (op) {
     case MS_OP_KEYS:
     case MS_OP_PAIRS: {
       if (m < 1 || m > (uint32_t)ms::kMaxBuckets || n >= 0xFFFFFFFFull) return 0;
-      return ms_ws_bytes(make_plan(n, m, s, op == MS_OP_PAIRS));
+      // The default shape depends on the bucket kind: size for both.
+      Shape t;
+      if (resolve_shape(opt, m, MS_BUCKET_SPLITTERS, &t) != MS_OK) return 0;
+      const size_t a = ms_ws_bytes(make_plan(n, m, s, op == MS_OP_PAIRS));
+      const size_t b = ms_ws_bytes(make_plan(n, m, t, op == MS_OP_PAIRS));
+      return a > b ? a : b;
     }
     case MS_OP_RADIX_SORT:
     case MS_OP_RADIX_SORT_PAIRS: {
@@ -406,7 +416,7 @@ ms_status ms_pairs(const uint32_t* d_keys_in, const uint32_t* d_vals_in, uint32_
   int fr = validate_fn(fn, m);
   if (fr != MS_OK) return (ms_status)fr;
   Shape s;
-  int sr = resolve_shape(opt, m, &s);
+  int sr = resolve_shape(opt, m, fn->kind, &s);
   if (sr != MS_OK) return (ms_status)sr;
   size_t need = ms_workspace_size(kv ? MS_OP_PAIRS : MS_OP_KEYS, n, m, 0, opt);
   if (n > 0 && (!d_ws || ws_bytes < need)) return MS_ERR_WORKSPACE;
@@ -424,7 +434,7 @@ ms_status ms_radix_sort(const uint32_t* d_keys_in, const uint32_t* d_vals_in,
   ms_status rc = check_common(d_keys_in, d_vals_in, d_keys_out, d_vals_out, n, m_digit, kv);
   if (rc != MS_OK) return rc;
   Shape s;
-  int sr = resolve_shape(opt, m_digit, &s);
+  int sr = resolve_shape(opt, m_digit, MS_BUCKET_SHIFT_MASK, &s);
   if (sr != MS_OK) return (ms_status)sr;
   size_t need =
       ms_workspace_size(kv ? MS_OP_RADIX_SORT_PAIRS : MS_OP_RADIX_SORT, n, m_digit, 0, opt);
@@ -571,6 +581,7 @@ ms_status ms_autotune(int op, const uint32_t* d_keys_in, const uint32_t* d_vals_
   struct Cand { int reorder, wpb, nw; uint32_t claim; };
   static const Cand kMulti[] = {{MS_REORDER_BLOCK, 8, 8, 0},  {MS_REORDER_BLOCK, 8, 4, 0},
                                 {MS_REORDER_BLOCK, 4, 8, 0},  {MS_REORDER_BLOCK, 4, 16, 0},
+                                {MS_REORDER_BLOCK, 16, 8, 0},
                                 {MS_REORDER_WAVE, 8, 8, 0},   {MS_REORDER_WAVE, 4, 16, 0},
                                 {MS_REORDER_NONE, 8, 8, 0}};
   static const Cand kBatch[] = {{MS_REORDER_BLOCK, 8, 8, 1},  {MS_REORDER_BLOCK, 8, 8, 4},

@@ -44,7 +44,7 @@ def lognormal_setup(n, fit_n=1 << 18):
     return keys, spl, fit
 
 
-SHAPES = [(1, 8, 8), (1, 4, 8), (2, 8, 8), (3, 8, 8)]
+SHAPES = [(1, 8, 8), (1, 4, 8), (1, 16, 8), (2, 8, 8), (3, 8, 8)]
 
 
 def test_learned_and_binary_search_match_oracle_with_cpu_model():

@@ -31,7 +31,7 @@ def say(*a):
 
 
 SHAPES = [  # (reorder, waves_per_block, items_per_lane)
-    (1, 8, 8), (1, 8, 4), (1, 4, 8), (1, 4, 16), (2, 8, 8), (2, 4, 16), (3, 8, 8)]
+    (1, 8, 8), (1, 8, 4), (1, 4, 8), (1, 4, 16), (1, 16, 8), (2, 8, 8), (2, 4, 16), (3, 8, 8)]
 
 
 def fn_for(kind, m, seed=0):
@@ -93,7 +93,7 @@ def test_prescan_methods(prescan):
               (524309, 32), (70001, 64)]
     for i, (n, m) in enumerate(combos):
         for kind in ("shift", "div", "splitters"):
-            for shape in ((1, 8, 8), (1, 4, 8), (1, 4, 16)):
+            for shape in ((1, 8, 8), (1, 4, 8), (1, 4, 16), (1, 16, 8)):
                 check_case(n, m, kind, kv=(i % 2 == 1), shape=shape, seed=5 * i + 1,
                            prescan=prescan)
 
