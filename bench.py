@@ -45,7 +45,75 @@ def parse():
     ap.add_argument("--chunks", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cold-reps", type=int, default=10,
+                    help="calls timed one by one after writing a 1 GiB scratch buffer (0: skip)")
+    ap.add_argument("--no-ceiling", action="store_true",
+                    help="skip the streaming-copy ceiling measurement")
     return ap.parse_args()
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def copy_ceiling(dev, reps=20, n=1 << 28):
+    """Measured streaming-copy rate (GB/s: 4 B read + 4 B written per word)
+    of the library's copy kernel on 2^28 words: the practical HBM ceiling the
+    roofline fraction is also quoted against."""
+    import torch
+
+    from paper_1701_01189_amd import binding as ms
+    a = torch.ones(n, dtype=torch.int32, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        ms.copy_u32(b, a)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        ms.copy_u32(b, a)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / reps
+    del a, b
+    return 8.0 * n / (t * 1e-3) / 1e9
+
+
+def cold_steps(step, reps, dev):
+    """Each call timed alone (HIP events on the call's stream) after a 1 GiB
+    scratch write that evicts the 256 MB Infinity Cache and the L2s (the
+    write itself is outside the timed region).  Returns per-call ms."""
+    import torch
+    scratch = torch.empty(1 << 28, dtype=torch.int32, device=dev)
+    hev = HipEvents(2 * reps)
+    out = []
+    for i in range(reps):
+        scratch.fill_(i)
+        torch.cuda.synchronize()
+        hev.record(2 * i)
+        step(None)
+        hev.record(2 * i + 1)
+        torch.cuda.synchronize()
+        out.append(hev.ms(2 * i, 2 * i + 1))
+    hev.close()
+    del scratch
+    return out
+
+
+def summary(ms_list, units):
+    import statistics
+    med = statistics.median(ms_list)
+    mean = sum(ms_list) / len(ms_list)
+    return {"reps": len(ms_list), "median_ms": round(med, 5), "mean_ms": round(mean, 5),
+            "value_median": round(units / (med * 1e-3) / 1e9, 3),
+            "value_mean": round(units / (mean * 1e-3) / 1e9, 3)}
 
 
 def workload(name):
@@ -87,6 +155,15 @@ class HipEvents:
             if self.hip.hipEventCreate(ctypes.byref(h)) != 0:
                 raise RuntimeError("hipEventCreate failed")
             self.ev.append(h.value)
+
+    def record(self, i):
+        """Record event i on torch's current stream (the one the library
+        launches on)."""
+        import torch
+        self.hip.hipEventRecord.argtypes = [self.ct.c_void_p, self.ct.c_void_p]
+        st = torch.cuda.current_stream().cuda_stream
+        if self.hip.hipEventRecord(self.ct.c_void_p(self.ev[i]), self.ct.c_void_p(st)) != 0:
+            raise RuntimeError("hipEventRecord failed")
 
     def ms(self, a, b):
         f = self.ct.c_float()
@@ -144,7 +221,7 @@ def cpu_baseline(kind, keys, vals, m, shift, budget_s):
             if el > budget_s or reps >= 50:
                 break
         return {"value": sample * reps / el / 1e9, "unit": "Gpairs/s" if v is not None else
-                "Gkeys/s", "cores": 1, "kind": "oracle",
+                "Gkeys/s", "cores": 1, "kind": "oracle", "cpu_model": cpu_model(),
                 "sample": "std::stable_sort of the first 2^24 elements, %d reps" % reps}
     mask = m - 1
     if kind == "range":
@@ -156,7 +233,7 @@ def cpu_baseline(kind, keys, vals, m, shift, budget_s):
             if el > budget_s or reps >= 50:
                 break
         return {"value": sample * reps / el / 1e9, "unit": "Gkeys/s", "cores": 1,
-                "kind": "oracle",
+                "kind": "oracle", "cpu_model": cpu_model(),
                 "sample": "the first 2^24 keys, std::upper_bound buckets, %d reps" % reps}
     while True:
         oracle.multisplit(keys, m, oracle.SHIFT_MASK, vals=vals, shift=shift, mask=mask)
@@ -165,7 +242,7 @@ def cpu_baseline(kind, keys, vals, m, shift, budget_s):
         if el > budget_s or reps >= 50:
             break
     return {"value": n * reps / el / 1e9, "unit": "Gpairs/s" if vals is not None else "Gkeys/s",
-            "cores": 1, "kind": "oracle",
+            "cores": 1, "kind": "oracle", "cpu_model": cpu_model(),
             "sample": "the full %d-element input, %d reps, single-threaded" % (n, reps)}
 
 
@@ -408,6 +485,7 @@ def main():
     K = args.steps
     hev = HipEvents(4 * K)
     evs = [[_Handle(hev.ev[4 * i + j]) for j in range(4)] for i in range(K)]
+    cev = HipEvents(K + 1)  # call boundaries (a radix sort records stages of its last pass only)
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
     t_start = torch.cuda.Event(enable_timing=True)
@@ -417,7 +495,9 @@ def main():
     for i in range(K):
         o = ms.Options(reorder=args.reorder, waves_per_block=args.waves,
                        items_per_lane=args.items, max_chunks=args.chunks, stage_events=evs[i])
+        cev.record(i)
         step(o)
+    cev.record(K)
     t_end.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
@@ -427,7 +507,13 @@ def main():
     for i in range(K):
         for s in range(3):
             stage[s] += hev.ms(4 * i + s, 4 * i + s + 1) / K
+    per_call = [cev.ms(i, i + 1) for i in range(K)]
     hev.close()
+    cev.close()
+    cold = None
+    if args.cold_reps > 0:
+        cold = summary(cold_steps(lambda _ev: step(opt), args.cold_reps, dev), n)
+    ceiling = None if args.no_ceiling else copy_ceiling(dev)
     # correctness spot check of the last step against the properties of the
     # unique stable result is done by the tests; here only a cheap sanity check
     units = n
@@ -465,7 +551,13 @@ def main():
                      "bytes_per_unit": 16 if kv else 8,
                      "whole_call_algorithmic_GBps": round(n * (20 if kv else 12) /
                                                           (ms_per_step * 1e-3) / 1e9, 1)},
+        "warm_per_call": summary(per_call, n),
     }
+    if cold is not None:
+        line["cold_per_call"] = cold
+    if ceiling is not None:
+        line["roofline"]["copy_ceiling_GBps"] = round(ceiling, 1)
+        line["roofline"]["frac_of_copy_ceiling"] = round(achieved / ceiling, 4)
     if radix:
         line["roofline"]["whole_call_algorithmic_GBps"] = round(
             n * 4 * (20 if kv else 12) / (ms_per_step * 1e-3) / 1e9, 1)
