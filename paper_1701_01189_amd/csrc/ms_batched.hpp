@@ -13,7 +13,10 @@
 // any post-scan item, by a workgroup that is already running and never
 // waits, so each awaited flag is eventually raised whatever the residency.
 // The wait is bounded all the same (spin_limit polls); on expiry the tile is
-// skipped and the status word records MS_ERR_TIMEOUT.
+// skipped and the status word records MS_ERR_TIMEOUT.  A workgroup takes
+// `claim` consecutive items per queue access and loads the next item's keys
+// (and values) while it works on the current one: inputs are ready from the
+// start, only the bucket bases of a post-scan item wait for its instance.
 #pragma once
 
 #include "ms_kernels.hpp"
@@ -57,7 +60,7 @@ static __global__ void __launch_bounds__(kSetupThreads) batched_setup_kernel(Bat
     const uint32_t i = i0 + e;
     if (i < a.num) {
       const uint64_t n = a.seg[i + 1] - a.seg[i];
-      sum += (uint32_t)((n + a.tile - 1) / a.tile);
+      sum += n == 0 ? 0u : ((uint32_t)n - 1u) / a.tile + 1u;  // no overflow near 2^32
     }
   }
   uint32_t total;
@@ -67,7 +70,7 @@ static __global__ void __launch_bounds__(kSetupThreads) batched_setup_kernel(Bat
     if (i < a.num) {
       const uint64_t n = a.seg[i + 1] - a.seg[i];
       a.tile_start[i] = pre;
-      pre += (uint32_t)((n + a.tile - 1) / a.tile);
+      pre += n == 0 ? 0u : ((uint32_t)n - 1u) / a.tile + 1u;
       a.done[i] = 0;
       a.ready[i] = 0;
       if (n == 0)
@@ -79,13 +82,22 @@ static __global__ void __launch_bounds__(kSetupThreads) batched_setup_kernel(Bat
     a.ctl[0] = 0;
     a.ctl[1] = 0;
   }
-  // tile -> instance map (the workgroup's own tile_start writes are visible
-  // after the barrier)
+  // tile -> instance map, one wavefront per instance so that the stores of
+  // an instance's tiles are coalesced (the workgroup's own tile_start writes
+  // are visible after the barrier)
+  // Each wavefront takes 64 consecutive instances, reads their tile ranges
+  // with one coalesced load and walks them with lane broadcasts.
   __syncthreads();
-  for (uint32_t e = 0; e < per; ++e) {
-    const uint32_t i = i0 + e;
-    if (i < a.num)
-      for (uint32_t t = a.tile_start[i]; t < a.tile_start[i + 1]; ++t) a.tile_inst[t] = i;
+  for (uint32_t base = w * kWave; base < a.num; base += kSetupThreads) {
+    const uint32_t i = base + lane;
+    const uint32_t t0 = i < a.num ? a.tile_start[i] : 0u;
+    const uint32_t t1 = i < a.num ? a.tile_start[i + 1] : 0u;
+    const uint32_t cnt = min((uint32_t)kWave, a.num - base);
+    for (uint32_t j = 0; j < cnt; ++j) {
+      const uint32_t s0 = __builtin_amdgcn_readlane(t0, j);
+      const uint32_t s1 = __builtin_amdgcn_readlane(t1, j);
+      for (uint32_t t = s0 + lane; t < s1; t += kWave) a.tile_inst[t] = base + j;
+    }
   }
 }
 
@@ -182,7 +194,30 @@ __global__ void __launch_bounds__(WPB* kWave) batched_kernel(BatchedArgs a) {
       }
       __syncthreads();
     };
-    for (uint32_t it = first; it < min(last, P); ++it) {
+    // Keys of work item `it` (a global tile index below P for a pre-scan
+    // item, P + tile for a post-scan item).  Lanes past the tile's end read
+    // the tile's first element, which exists, and are masked out later.
+    uint32_t k[NW], v[NW];
+    auto load_item = [&](uint32_t it, auto vals_tag) {
+      constexpr bool with_vals = decltype(vals_tag)::value;
+      const uint32_t tg = it < P ? it : it - P;
+      const uint32_t i = a.tile_inst[tg];
+      const uint32_t t = tg - a.tile_start[i];
+      const uint32_t s0 = (uint32_t)a.seg[i];
+      const uint32_t tcount = min((uint32_t)T, (uint32_t)(a.seg[i + 1] - s0) - t * T);
+      const uint32_t tb = s0 + t * T;
+      const uint32_t* pk = a.keys_in + tb + wbase + lane;
+      const uint32_t* pv = a.vals_in + tb + wbase + lane;
+#pragma unroll
+      for (int j = 0; j < NW; ++j) {
+        const bool valid = wbase + (uint32_t)(j * kWave) + lane < tcount;
+        k[j] = __builtin_nontemporal_load(valid ? pk + j * kWave : a.keys_in + tb);
+        if (KV && with_vals) v[j] = __builtin_nontemporal_load(valid ? pv + j * kWave : a.vals_in + tb);
+      }
+    };
+    const uint32_t pre_end = min(last, P);
+    if (first < pre_end) load_item(first, std::false_type{});
+    for (uint32_t it = first; it < pre_end; ++it) {
       const uint32_t i = a.tile_inst[it];
       if (i != pub_inst) {
         if (pub_count) publish();
@@ -193,17 +228,26 @@ __global__ void __launch_bounds__(WPB* kWave) batched_kernel(BatchedArgs a) {
       const uint32_t tiles = a.tile_start[i + 1] - a.tile_start[i];
       const uint32_t n_i = (uint32_t)(a.seg[i + 1] - a.seg[i]);
       const uint32_t tcount = min((uint32_t)T, n_i - t * T);
-      const uint32_t tb = (uint32_t)a.seg[i] + t * T;
       uint32_t* Hi = a.H + (size_t)m * a.tile_start[i];
       uint32_t cnt[MB];
 #pragma unroll
       for (int q = 0; q < MB; ++q) cnt[q] = 0;
-      const uint32_t* pk = a.keys_in + tb + wbase + lane;
+      // bucket ids of this tile, then the next item's keys are requested
+      // (software pipelining across the claim) while the histogram is solved
+      uint32_t bk[NW];
 #pragma unroll
       for (int j = 0; j < NW; ++j) {
         const bool valid = wbase + (uint32_t)(j * kWave) + lane < tcount;
-        const uint32_t b = valid ? bf_pre(pk[j * kWave]) : 0u;
-        window_histogram<BITS>(b, ballot(valid), ls, cnt);
+        bk[j] = valid ? bf_pre(k[j]) : 0u;
+      }
+      if (it + 1 < P)
+        load_item(it + 1, std::false_type{});
+      else if (it + 1 < last)
+        load_item(it + 1, std::true_type{});  // the claim's first post-scan item
+#pragma unroll
+      for (int j = 0; j < NW; ++j) {
+        const bool valid = wbase + (uint32_t)(j * kWave) + lane < tcount;
+        window_histogram<BITS>(bk[j], ballot(valid), ls, cnt);
       }
 #pragma unroll
       for (int q = 0; q < MB; ++q) {
@@ -224,8 +268,12 @@ __global__ void __launch_bounds__(WPB* kWave) batched_kernel(BatchedArgs a) {
 
     // ---- post-scan items of this claim; the wait (an acquire) is done
     // once per instance ----
+    // (the first post-scan item's keys and values were requested by the
+    // last pre-scan item of this claim, or are requested here)
     uint32_t seen = 0xFFFFFFFFu;
-    for (uint32_t it = (first > P ? first : P); it < last; ++it) {
+    const uint32_t post_first = first > P ? first : P;
+    if (post_first < last && first >= P) load_item(post_first, std::true_type{});
+    for (uint32_t it = post_first; it < last; ++it) {
       const uint32_t tg = it - P;
       const uint32_t i = a.tile_inst[tg];
       if (i != seen) {
@@ -245,6 +293,7 @@ __global__ void __launch_bounds__(WPB* kWave) batched_kernel(BatchedArgs a) {
         seen = s_flag ? i : 0xFFFFFFFFu;
         if (!s_flag) {
           __syncthreads();
+          if (it + 1 < last) load_item(it + 1, std::true_type{});
           continue;  // instance not published in time: tile skipped, status set
         }
       }
@@ -253,26 +302,17 @@ __global__ void __launch_bounds__(WPB* kWave) batched_kernel(BatchedArgs a) {
       const uint32_t s0 = (uint32_t)a.seg[i];
       const uint32_t n_i = (uint32_t)(a.seg[i + 1] - s0);
       const uint32_t tcount = min((uint32_t)T, n_i - t * T);
-      const uint32_t tb = s0 + t * T;
       const uint32_t* Hi = a.H + (size_t)m * a.tile_start[i];
       for (uint32_t b = tid; b < m; b += WPB * kWave) s_run[b] = s0 + Hi[b * tiles + t];
-      uint32_t k[NW], v[NW];
-      const uint32_t* pk = a.keys_in + tb + wbase + lane;
-      const uint32_t* pv = a.vals_in + tb + wbase + lane;
-#pragma unroll
-      for (int j = 0; j < NW; ++j) {
-        // lanes past the end read the tile's first element, which exists
-        const bool valid = wbase + (uint32_t)(j * kWave) + lane < tcount;
-        k[j] = __builtin_nontemporal_load(valid ? pk + j * kWave : a.keys_in + tb);
-        if (KV) v[j] = __builtin_nontemporal_load(valid ? pv + j * kWave : a.vals_in + tb);
-      }
       __syncthreads();
       TileCtx<KV> ctx{s_keys, s_vals, s_bk, s_cnt + w * kCntStride, s_cnt, s_run, s_delta,
                       s_tmp, a.keys_out, a.vals_out, m, tcount, w, lane, tid};
+      // the next item's loads go out once this tile sits in LDS
+      auto next = [&] { if (it + 1 < last) load_item(it + 1, std::true_type{}); };
       if (tcount == (uint32_t)T)
-        tile_rank_reorder_write<BITS, KV, WPB, NW, true>(bf_post, k, v, ctx, [] {});
+        tile_rank_reorder_write<BITS, KV, WPB, NW, true>(bf_post, k, v, ctx, next);
       else
-        tile_rank_reorder_write<BITS, KV, WPB, NW, false>(bf_post, k, v, ctx, [] {});
+        tile_rank_reorder_write<BITS, KV, WPB, NW, false>(bf_post, k, v, ctx, next);
       __syncthreads();
     }
   }
