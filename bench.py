@@ -13,7 +13,8 @@ written once), timed with HIP events on the stream the kernels run on; and
 the CPU oracle timed on the host cores.
 
 Other workloads (--workload): keys_2e20_m8, keys_2e28_m<m>, pairs_2e28_m<m>,
-radix_pairs_2e28, radix_keys_2e28, and range_2e27_m256: n = 2^27 lognormal
+radix_pairs_2e28, radix_keys_2e28, hist_2e<k>_m<m> and histrange_2e<k>_m<m>
+(device-wide histograms, even or range bins), and range_2e27_m256: n = 2^27 lognormal
 (mu 20, sigma 2) keys saturated to 32 bits (seed 103), 256 range buckets at
 quantiles of a 2^16-key sample (seed 1031); the learned identifier (fit on the
 GPU from 2^20 keys, seed 1032) is timed against the binary search over the
@@ -134,6 +135,10 @@ def workload(name):
         return "copy", 1 << 28, 1, 0, 7
     if name == "batched_4096_m64":
         return "batched", 4096, 64, 8, 104
+    if name.startswith("hist_") or name.startswith("histrange_"):
+        # hist_2e25_m32: even bins (k >> (32 - log2 m)); histrange_: m-1 random splitters
+        size, mm = name.split("_")[1], int(name.split("_m")[1])
+        return name.split("_")[0], 1 << int(size[2:]), mm, 32 - (mm - 1).bit_length(), 110
     raise SystemExit("unknown workload %s" % name)
 
 
@@ -338,6 +343,90 @@ def bench_batched(args, num, m, shift, seed, dev):
     print(json.dumps(line), flush=True)
 
 
+def bench_hist(args, kind, n, m, shift, seed, dev):
+    """Device-wide histogram (Section 7.3) of n uniform 32-bit keys: even bins
+    f(k) = k >> (32 - log2 m), or range bins over m-1 sorted random splitters
+    (seed 113), as in the paper's Even and Range experiments (2^25 elements,
+    m <= 256).  One step = one ms_histogram call (zero the output, pre-scan with
+    atomic accumulation)."""
+    import numpy as np
+    import torch
+
+    from paper_1701_01189_amd import binding as ms
+    from paper_1701_01189_amd import inputs
+    keys = inputs.uniform_u32(seed, n)
+    dk = torch.from_numpy(keys.view(np.int32)).to(dev)
+    spl = np.sort(inputs.uniform_u32(113, m - 1)) if kind == "histrange" else None
+    ds = torch.from_numpy(spl.view(np.int32)).to(dev) if spl is not None else None
+    fn = ms.BucketFn.splitter(ds) if ds is not None else ms.BucketFn.shift_mask(shift, m - 1)
+    base = dict(reorder=args.reorder, waves_per_block=args.waves, items_per_lane=args.items,
+                max_chunks=args.chunks)
+    hist = torch.empty(m, dtype=torch.int32, device=dev)
+    ws = torch.empty(max(256, ms.workspace_size(ms.OP_HISTOGRAM, n, m, 0, ms.Options(**base))),
+                     dtype=torch.uint8, device=dev)
+
+    def step(ev):
+        ms.histogram(dk, m, fn, hist=hist, options=ms.Options(stage_events=ev, **base), ws=ws)
+    t_eager, st = time_steps(step, args.steps, args.warmup)
+    # A call is ~20-200 us of GPU work, close to the host's own cost of a
+    # call from Python; replaying the call from a HIP graph measures the GPU.
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        step(None)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step(None)
+    for _ in range(args.warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / args.steps
+    value = n / (t * 1e-3) / 1e9
+    pre_gbps = 4.0 * n / (st[0] * 1e-3) / 1e9
+    line = {
+        "metric": METRIC, "value": round(value, 3), "unit": "Gkeys/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(t, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "m": m,
+                   "bins": "range (m-1 random splitters)" if spl is not None else "even (k >> %d)" % shift,
+                   "seed": seed, **base},
+        "hipgraph": True,
+        "eager_value": round(n / (t_eager * 1e-3) / 1e9, 3),
+        "stage_ms": {"prescan": round(st[0], 5), "reduce": round(st[1], 5)},
+        "roofline": {"bound": "hbm", "kernel": "prescan", "achieved": round(pre_gbps, 1),
+                     "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": round(pre_gbps / HBM_PEAK_GBPS, 4),
+                     "traffic": traffic_for("prescan", args.workload, n), "bytes_per_unit": 4},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        sample = min(n, 1 << 24)
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            if spl is not None:
+                oracle.histogram(keys[:sample], m, oracle.SPLITTERS, splitters=spl)
+            else:
+                oracle.histogram(keys[:sample], m, oracle.SHIFT_MASK, shift=shift, mask=m - 1)
+            reps += 1
+            el = time.perf_counter() - t0
+            if el > args.cpu_seconds or reps >= 50:
+                break
+        line["cpu_baseline"] = {"value": sample * reps / el / 1e9, "unit": "Gkeys/s", "cores": 1,
+                                "kind": "oracle", "cpu_model": cpu_model(),
+                                "sample": "the first 2^24 keys, %d reps" % reps}
+    print(json.dumps(line), flush=True)
+
+
 def bench_copy(args, n, dev):
     """Streaming copy of n words (the measured HBM ceiling, and the known
     byte count that scales the FETCH_SIZE / WRITE_SIZE counters)."""
@@ -456,6 +545,8 @@ def main():
         return bench_copy(args, n, dev)
     if kind == "batched":
         return bench_batched(args, n, m, shift, seed, dev)
+    if kind in ("hist", "histrange"):
+        return bench_hist(args, kind, n, m, shift, seed, dev)
     keys = inputs.uniform_u32(seed, n)
     vals = inputs.index_values(n) if kv else None
     dk = torch.from_numpy(keys.view(np.int32)).to(dev)

@@ -175,7 +175,8 @@ enum {
   MS_OP_BATCHED = 2,
   MS_OP_RADIX_SORT = 3,
   MS_OP_RADIX_SORT_PAIRS = 4,
-  MS_OP_LEARNED_FIT = 5
+  MS_OP_LEARNED_FIT = 5,
+  MS_OP_HISTOGRAM = 6
 };
 
 /*
@@ -212,6 +213,20 @@ ms_status ms_pairs(const uint32_t* d_keys_in, const uint32_t* d_vals_in,
                    uint32_t* d_offsets, size_t n, uint32_t m,
                    const ms_bucket_fn* fn, void* d_ws, size_t ws_bytes,
                    const ms_options* opt, void* stream);
+
+/*
+ * Device-wide histogram (Section 7.3): d_hist[j] = number of the n keys with
+ * fn(key) = j, for j < m.  It is the multisplit pre-scan with every
+ * subproblem's counts added into d_hist by atomics; no key moves.  Even bins
+ * are SHIFT_MASK or DIV buckets, range bins SPLITTERS or LEARNED buckets.
+ *   d_keys   n uint32 keys (device).  n = 0 writes m zeros.
+ *   d_hist   m uint32 (device), overwritten; must not overlap d_keys.
+ *   d_ws     ms_workspace_size(MS_OP_HISTOGRAM, n, m, 0, opt) bytes.
+ * opt->d_mispredicts is not updated by this call.  Errors as ms_keys.
+ */
+ms_status ms_histogram(const uint32_t* d_keys, size_t n, uint32_t m,
+                       const ms_bucket_fn* fn, uint32_t* d_hist, void* d_ws,
+                       size_t ws_bytes, const ms_options* opt, void* stream);
 
 /*
  * LSD radix sort built from multisplit passes (Section 7.1): with r =

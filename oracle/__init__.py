@@ -57,6 +57,8 @@ def _load():
     u32, u64, i32 = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
     lib.or_bucket_ids.argtypes = [P32, u64, u32, i32, u32, u32, P32, P32]
     lib.or_bucket_ids.restype = i32
+    lib.or_histogram.argtypes = [P32, u64, u32, i32, u32, u32, P32, P32]
+    lib.or_histogram.restype = i32
     lib.or_multisplit.argtypes = [P32, P32, u64, u32, i32, u32, u32, P32, P32, P32, P32]
     lib.or_multisplit.restype = i32
     lib.or_radix_sort.argtypes = [P32, P32, u64, P32, P32]
@@ -93,6 +95,18 @@ def bucket_ids(keys, m, kind, shift=0, mask=0, divisor=0, splitters=None):
     spl = _c32(splitters) if splitters is not None else None
     p0, p1 = _params(kind, shift, mask, divisor)
     rc = _load().or_bucket_ids(_u32p(keys), len(keys), m, kind, p0, p1, _u32p(spl), _u32p(out))
+    if rc:
+        raise ValueError("bucket id outside [0, m)")
+    return out
+
+
+def histogram(keys, m, kind, shift=0, mask=0, divisor=0, splitters=None):
+    """Section 7.3: number of keys per bucket (m uint32)."""
+    keys = _c32(keys)
+    out = np.empty(m, dtype=np.uint32)
+    spl = _c32(splitters) if splitters is not None else None
+    p0, p1 = _params(kind, shift, mask, divisor)
+    rc = _load().or_histogram(_u32p(keys), len(keys), m, kind, p0, p1, _u32p(spl), _u32p(out))
     if rc:
         raise ValueError("bucket id outside [0, m)")
     return out

@@ -23,6 +23,8 @@
 //     std::stable_sort is that definition.
 //   * batched multisplit -- the stable multisplit applied to each segment on
 //     its own; offsets are relative to the segment start.
+//   * device-wide histogram -- Section 7.3: the number of keys per bucket,
+//     h_j = #{i : f(u_i) = j} (the same h_j as in Eq. 1), counted in one pass.
 //   * learned bucket identifier -- a two-stage piecewise-linear model of the
 //     bucket as a function of the key (an even split of the key range into
 //     leaves, then a least-squares line per leaf) fit in double precision,
@@ -76,6 +78,19 @@ int or_bucket_ids(const uint32_t* keys, uint64_t n, uint32_t m, int kind,
   for (uint64_t i = 0; i < n; ++i) {
     out[i] = bucket_of(kind, p0, p1, spl, m, keys[i]);
     if (out[i] >= m) return -1;
+  }
+  return 0;
+}
+
+// Histogram of the bucket ids (Section 7.3): hist[j] = #{i : f(keys[i]) = j}.
+// Returns 0, or -1 if a key maps outside [0, m).
+int or_histogram(const uint32_t* keys, uint64_t n, uint32_t m, int kind,
+                 uint32_t p0, uint32_t p1, const uint32_t* spl, uint32_t* hist) {
+  for (uint32_t j = 0; j < m; ++j) hist[j] = 0;
+  for (uint64_t i = 0; i < n; ++i) {
+    const uint32_t b = bucket_of(kind, p0, p1, spl, m, keys[i]);
+    if (b >= m) return -1;
+    hist[b] += 1;
   }
   return 0;
 }

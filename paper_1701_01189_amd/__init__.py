@@ -8,8 +8,10 @@ binding (``binding``), the in-tree build (``build``) and the seeded input
 generators (``inputs``).  The native library is loaded on first use.
 """
 from .binding import (BUCKET_DIV, BUCKET_LEARNED, BUCKET_SHIFT_MASK, BUCKET_SPLITTERS,
-                      MODEL_FLOATS, OP_BATCHED, OP_KEYS, OP_LEARNED_FIT, OP_PAIRS, OP_RADIX_SORT, OP_RADIX_SORT_PAIRS,
+                      MODEL_FLOATS, OP_BATCHED, OP_HISTOGRAM, OP_KEYS, OP_LEARNED_FIT, OP_PAIRS, OP_RADIX_SORT,
+                      OP_RADIX_SORT_PAIRS,
                       PRESCAN_AUTO, PRESCAN_BALLOT, PRESCAN_LANES,
                       REORDER_AUTO, REORDER_BLOCK, REORDER_NONE, REORDER_WAVE, BucketFn,
-                      MultisplitError, Options, batched, batched_status, copy_u32, keys, learned_fit, pairs, radix_sort,
+                      MultisplitError, Options, batched, batched_status, copy_u32, histogram, keys, learned_fit, pairs,
+                      radix_sort,
                       workspace_size)

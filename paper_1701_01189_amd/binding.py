@@ -20,7 +20,8 @@ STATUS = {0: "MS_OK", -1: "MS_ERR_INVALID_ARG", -2: "MS_ERR_WORKSPACE", -3: "MS_
 BUCKET_SHIFT_MASK, BUCKET_DIV, BUCKET_SPLITTERS, BUCKET_LEARNED = 0, 1, 2, 3
 REORDER_AUTO, REORDER_BLOCK, REORDER_WAVE, REORDER_NONE = 0, 1, 2, 3
 PRESCAN_AUTO, PRESCAN_BALLOT, PRESCAN_LANES = 0, 1, 2
-OP_KEYS, OP_PAIRS, OP_BATCHED, OP_RADIX_SORT, OP_RADIX_SORT_PAIRS, OP_LEARNED_FIT = range(6)
+OP_KEYS, OP_PAIRS, OP_BATCHED, OP_RADIX_SORT, OP_RADIX_SORT_PAIRS, OP_LEARNED_FIT, OP_HISTOGRAM = \
+    range(7)
 MODEL_LEAVES = 256
 MODEL_FLOATS = 2 + 2 * MODEL_LEAVES
 
@@ -73,6 +74,9 @@ def lib():
     L.ms_pairs.argtypes = [vp, vp, vp, vp, vp, sz, u32, ctypes.POINTER(BucketFnC), vp, sz,
                            ctypes.POINTER(OptionsC), vp]
     L.ms_pairs.restype = i32
+    L.ms_histogram.argtypes = [vp, sz, u32, ctypes.POINTER(BucketFnC), vp, vp, sz,
+                               ctypes.POINTER(OptionsC), vp]
+    L.ms_histogram.restype = i32
     L.ms_radix_sort.argtypes = [vp, vp, vp, vp, sz, u32, vp, sz, ctypes.POINTER(OptionsC), vp]
     L.ms_radix_sort.restype = i32
     L.ms_batched.argtypes = [vp, vp, vp, vp, vp, u32, sz, u32, ctypes.POINTER(BucketFnC), vp, vp,
@@ -233,6 +237,23 @@ def pairs(keys_in, vals_in, m, fn, keys_out=None, vals_out=None, offsets=None, o
                         ctypes.byref(o) if o is not None else None, _stream(stream))
     _check(rc, "ms_pairs")
     return keys_out, vals_out, offsets
+
+
+def histogram(keys_in, m, fn, hist=None, options=None, stream=None, ws=None):
+    """Device-wide histogram of fn over a 32-bit key tensor: hist[j] = number
+    of keys in bucket j.  Returns hist (m int32, read as uint32)."""
+    import torch
+    n = keys_in.numel()
+    if hist is None:
+        hist = torch.empty(m, dtype=torch.int32, device=keys_in.device)
+    w, wb = _workspace(OP_HISTOGRAM, n, m, keys_in.device, options, ws=ws)
+    f = fn.c()
+    o = options.c() if options is not None else None
+    rc = lib().ms_histogram(_u32(keys_in, "keys_in"), n, m, ctypes.byref(f), _u32(hist, "hist"),
+                            _ptr(w), wb, ctypes.byref(o) if o is not None else None,
+                            _stream(stream))
+    _check(rc, "ms_histogram")
+    return hist
 
 
 def radix_sort(keys_in, vals_in=None, bits_per_pass=8, keys_out=None, vals_out=None,

@@ -102,6 +102,10 @@ prescan_kernel(const uint32_t* __restrict__ keys, Plan plan, BucketParams bp,
     for (uint32_t i = threadIdx.x; i < NB * kWave; i += WPB * kWave) s_lane[i] = 0u;
   stage_bucket_tables<Kind>(bp, &tables);
   __syncthreads();
+  // A chunk's count of bucket b goes to its column of H.
+  auto emit = [&](uint32_t b, uint32_t v) {
+    H[b * plan.L0 + blockIdx.x * GPB + (wave_id() / WPG)] = v;
+  };
   auto lane_count = [&](uint32_t b, uint32_t lane) {
     __hip_atomic_fetch_add(&s_lane[b * kWave + lane], 1u, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -173,7 +177,7 @@ prescan_kernel(const uint32_t* __restrict__ keys, Plan plan, BucketParams bp,
 #pragma unroll
       for (int t = 0; t < MB; ++t) {
         uint32_t b = lane + kWave * t;
-        if (b < plan.m) H[b * plan.L0 + c] = cnt[t];
+        if (b < plan.m) emit(b, cnt[t]);
       }
     }
   } else if (LANES) {
@@ -182,7 +186,7 @@ prescan_kernel(const uint32_t* __restrict__ keys, Plan plan, BucketParams bp,
     if (c < plan.L0) {
       for (uint32_t b = w; b < plan.m; b += WPB) {
         const uint32_t s = wave_inclusive_scan(s_lane[b * kWave + lane], lane);
-        if (lane == kWave - 1) H[b * plan.L0 + c] = s;
+        if (lane == kWave - 1) emit(b, s);
       }
     }
   } else {
@@ -197,7 +201,7 @@ prescan_kernel(const uint32_t* __restrict__ keys, Plan plan, BucketParams bp,
         uint32_t s = 0;
 #pragma unroll
         for (int ww = 0; ww < WPB; ++ww) s += s_hist[ww * kMaxBuckets + b];
-        H[b * plan.L0 + c] = s;
+        emit(b, s);
       }
     }
   }

@@ -48,20 +48,26 @@ bool shape_supported(const Shape& s) { return ms::post_shape_supported(s.mode, s
 // and 8 x 8 for those that search LDS tables (their extra registers make
 // the larger tile slower).  Measured on MI355X with 2^25 pairs, 2^28 keys,
 // 2^28-pair radix sort and 2^27 range keys.  The paper's own defaults are 8
-// warps x 4 windows of 32 (Section 6, "Parameters").  `kind` < 0: unknown
-// (the workspace query takes the larger of the two plans).
+// warps x 4 windows of 32 (Section 6, "Parameters").  With wave-level or
+// no reordering the default is 8 x 8 (4 x 16 for wave level at m <= 64).
 int resolve_shape(const ms_options* opt, uint32_t m, int kind, Shape* s) {
   const bool table_kind = kind == MS_BUCKET_SPLITTERS || kind == MS_BUCKET_LEARNED;
   s->mode = ms::kBlock;
-  s->wpb = m <= 64 ? 4 : (table_kind ? 8 : 16);
-  s->nw = m <= 64 ? 16 : 8;
+  if (opt) {
+    if (opt->reorder < 0 || opt->reorder > MS_REORDER_NONE) return MS_ERR_INVALID_ARG;
+    if (opt->reorder == MS_REORDER_WAVE) s->mode = ms::kWaveMode;
+    if (opt->reorder == MS_REORDER_NONE) s->mode = ms::kDirect;
+  }
+  if (s->mode == ms::kBlock) {
+    s->wpb = m <= 64 ? 4 : (table_kind ? 8 : 16);
+    s->nw = m <= 64 ? 16 : 8;
+  } else {
+    s->wpb = (s->mode == ms::kWaveMode && m <= 64) ? 4 : 8;
+    s->nw = (s->mode == ms::kWaveMode && m <= 64) ? 16 : 8;
+  }
   s->max_chunks = 0;
   int prescan = MS_PRESCAN_AUTO;
   if (opt) {
-    if (opt->reorder < 0 || opt->reorder > MS_REORDER_NONE) return MS_ERR_INVALID_ARG;
-    if (opt->reorder == MS_REORDER_BLOCK) s->mode = ms::kBlock;
-    if (opt->reorder == MS_REORDER_WAVE) s->mode = ms::kWaveMode;
-    if (opt->reorder == MS_REORDER_NONE) s->mode = ms::kDirect;
     if (opt->waves_per_block) s->wpb = opt->waves_per_block;
     if (opt->items_per_lane) s->nw = opt->items_per_lane;
     if (opt->max_chunks < 0) return MS_ERR_INVALID_ARG;
@@ -366,7 +372,8 @@ size_t ms_workspace_size(int op, size_t n, uint32_t m, uint32_t num_inst, const 
   if (resolve_shape(opt, m, MS_BUCKET_SHIFT_MASK, &s) != MS_OK) return 0;
   switch (op) {
     case MS_OP_KEYS:
-    case MS_OP_PAIRS: {
+    case MS_OP_PAIRS:
+    case MS_OP_HISTOGRAM: {
       if (m < 1 || m > (uint32_t)ms::kMaxBuckets || n >= 0xFFFFFFFFull) return 0;
       // The default shape depends on the bucket kind: size for both.
       Shape t;
@@ -422,6 +429,46 @@ ms_status ms_pairs(const uint32_t* d_keys_in, const uint32_t* d_vals_in, uint32_
   if (n > 0 && (!d_ws || ws_bytes < need)) return MS_ERR_WORKSPACE;
   return run_multisplit(d_keys_in, kv ? d_vals_in : nullptr, d_keys_out, d_vals_out, d_offsets,
                         n, m, fn, d_ws, s, opt, (hipStream_t)stream);
+}
+
+ms_status ms_histogram(const uint32_t* d_keys, size_t n, uint32_t m, const ms_bucket_fn* fn,
+                       uint32_t* d_hist, void* d_ws, size_t ws_bytes, const ms_options* opt,
+                       void* stream) {
+  if (m < 1 || m > (uint32_t)ms::kMaxBuckets || n >= 0xFFFFFFFFull || !d_hist)
+    return MS_ERR_INVALID_ARG;
+  if (n > 0) {
+    if (!d_keys) return MS_ERR_INVALID_ARG;
+    const char* k = (const char*)d_keys;
+    const char* h = (const char*)d_hist;
+    if (k < h + (size_t)m * 4 && h < k + n * 4) return MS_ERR_INVALID_ARG;  // overlap
+  }
+  int fr = validate_fn(fn, m);
+  if (fr != MS_OK) return (ms_status)fr;
+  Shape s;
+  int sr = resolve_shape(opt, m, fn->kind, &s);
+  if (sr != MS_OK) return (ms_status)sr;
+  const size_t need = ms_workspace_size(MS_OP_HISTOGRAM, n, m, 0, opt);
+  if (n > 0 && (!d_ws || ws_bytes < need)) return MS_ERR_WORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  if (n == 0) return fill(d_hist, m, 0, st) == hipSuccess ? MS_OK : MS_ERR_HIP;
+  // Section 7.3 names two ways to combine the subproblems' counts: store
+  // them and reduce per bucket, or add them into the output with atomics.
+  // The first is used: with ~2^11 subproblems, the atomic additions to each
+  // bin serialise in L2 (2^25 keys, m = 32: 245 us against 25 us).  Here the
+  // reduction is the row-total output of the scan kernel.
+  Plan p = make_plan(n, m, s, false);
+  Workspace w = carve(d_ws, p);
+  BucketParams bp = make_params(fn, m, nullptr);
+  if (record(opt, 0, st) != hipSuccess) return MS_ERR_HIP;
+  ms::PreArgs pa{d_keys, p, bp, w.H, s.mode, s.hist, st};
+  if (pre_by_kind(fn->kind, pa, (int)ceil_log2(m)) != hipSuccess) return MS_ERR_HIP;
+  if (record(opt, 1, st) != hipSuccess) return MS_ERR_HIP;
+  hipLaunchKernelGGL(ms::scan_rows_kernel, dim3(m), dim3(ms::kScanThreads), 0, st, w.H, p.L0,
+                     d_hist);
+  if (hipGetLastError() != hipSuccess) return MS_ERR_HIP;
+  for (int e = 2; e < 4; ++e)
+    if (record(opt, e, st) != hipSuccess) return MS_ERR_HIP;
+  return MS_OK;
 }
 
 ms_status ms_radix_sort(const uint32_t* d_keys_in, const uint32_t* d_vals_in,

@@ -82,6 +82,18 @@ def test_host_validation_rejects_before_launch(L):
     # pairs: values missing on one side
     assert L.ms_pairs(ki, None, ko, fake(0x30000000), None, n, 32, ctypes.byref(fn), ws, need,
                       None, None) == -1
+    # histogram: missing or overlapping output, bad m, small workspace, bad bucket function
+    hh = fake(0x40000000)
+    assert L.ms_histogram(ki, n, 32, ctypes.byref(fn), None, ws, need, None, None) == -1
+    assert L.ms_histogram(ki, n, 0, ctypes.byref(fn), hh, ws, need, None, None) == -1
+    assert L.ms_histogram(ki, n, 32, ctypes.byref(fn), fake(0x1000000 + 64), ws, need, None,
+                          None) == -1
+    assert L.ms_histogram(ki, n, 32, ctypes.byref(fn), fake(0x1000000 - 64), ws, need, None,
+                          None) == -1
+    assert L.ms_histogram(ki, n, 32, ctypes.byref(fn), hh, ws, need - 1, None, None) == -2
+    bad = BucketFnC(0, 27, 63, 0, None, None)
+    assert L.ms_histogram(ki, n, 32, ctypes.byref(bad), hh, ws, need, None, None) == -4
+    assert L.ms_workspace_size(6, n, 32, 0, None) == need
     # radix sort: bits per pass out of range
     assert L.ms_radix_sort(ki, None, ko, None, n, 9, ws, 1 << 30, None, None) == -1
     assert L.ms_radix_sort(ki, None, ko, None, n, 0, ws, 1 << 30, None, None) == -1
@@ -98,3 +110,15 @@ def test_workspace_sizes(L):
     assert L.ms_workspace_size(0, 1000, 0, 0, None) == 0
     o = OptionsC(2, 8, 8, 0, None, None)
     assert L.ms_workspace_size(1, 1 << 25, 32, 0, ctypes.byref(o)) > 0
+
+
+def test_default_shape_for_every_reorder_mode(L):
+    """Only the reordering mode set: the library picks a supported tile shape
+    for every m (a wave-level or direct call at m > 64 must not inherit the
+    block-level 16 x 8 default)."""
+    from paper_1701_01189_amd.binding import OptionsC
+    for mode in (0, 1, 2, 3):
+        for m in (1, 2, 32, 64, 65, 200, 256):
+            o = OptionsC(mode, 0, 0, 0, None, None)
+            for op in (0, 1, 6):
+                assert L.ms_workspace_size(op, 1 << 20, m, 0, ctypes.byref(o)) > 0, (mode, m, op)
