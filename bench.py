@@ -127,6 +127,12 @@ def workload(name):
         m = int(name.split("_m")[1])
         r = (m - 1).bit_length()
         return name.split("_")[0], 1 << 28, m, 32 - r, 100
+    if name.startswith("ident_"):
+        # ident_keys_2e25_b5: keys uniform in [0, 2^b), identity buckets f(k) = k,
+        # m = 2^b (the paper's multisplit-with-identity-buckets sweep, Section 7.1)
+        parts = name.split("_")
+        bits = int(parts[3][1:])
+        return parts[1] + "_ident", 1 << int(parts[2][2:]), 1 << bits, 0, 120 + bits
     if name in ("radix_pairs_2e28", "radix_keys_2e28"):
         return name.rsplit("_", 1)[0], 1 << 28, 256, 0, 105
     if name == "range_2e27_m256":
@@ -537,7 +543,7 @@ def main():
     if not os.path.exists(b.LIB):
         b.build(force=True)
     kind, n, m, shift, seed = workload(args.workload)
-    kv = kind.endswith("pairs")
+    kv = kind.startswith("pairs") or kind == "radix_pairs"
     dev = torch.device("cuda:0")
     if kind == "range":
         return bench_range(args, n, m, seed, dev)
@@ -547,7 +553,12 @@ def main():
         return bench_batched(args, n, m, shift, seed, dev)
     if kind in ("hist", "histrange"):
         return bench_hist(args, kind, n, m, shift, seed, dev)
+    ident = kind.endswith("_ident")
+    if ident:
+        kind = kind[:-len("_ident")]
     keys = inputs.uniform_u32(seed, n)
+    if ident:
+        keys &= np.uint32(m - 1)
     vals = inputs.index_values(n) if kv else None
     dk = torch.from_numpy(keys.view(np.int32)).to(dev)
     dv = torch.from_numpy(vals.view(np.int32)).to(dev) if kv else None
@@ -628,7 +639,8 @@ def main():
         "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "m": m,
-                   "bucket": "shift_mask" if not radix else "radix 4 x 8-bit digits",
+                   "bucket": ("radix 4 x 8-bit digits" if radix else
+                              "identity (keys < m)" if ident else "shift_mask"),
                    "shift": shift, "kv": kv, "seed": seed,
                    "reorder": args.reorder, "waves_per_block": args.waves,
                    "items_per_lane": args.items},

@@ -215,3 +215,24 @@ def test_repeated_calls_deterministic():
             np.testing.assert_array_equal(cur[0], ek)
         for a, b in zip(ref, cur):
             np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("bits", [1, 2, 3, 4, 5, 6, 7, 8])
+def test_identity_buckets_sort_small_keys(bits):
+    """Identity buckets over keys of `bits` bits (f(k) = k, m = 2^bits): the
+    multisplit is then the stable sort of those keys (Section 7.1's sweep)."""
+    from paper_1701_01189_amd import binding as ms
+    m = 1 << bits
+    n = (1 << 20) + 7
+    keys = inputs.uniform_u32(120 + bits, n) & np.uint32(m - 1)
+    vals = inputs.index_values(n)
+    order = np.argsort(keys, kind="stable")
+    ek, ev, eo = oracle.multisplit(keys, m, oracle.SHIFT_MASK, vals=vals, shift=0, mask=m - 1)
+    np.testing.assert_array_equal(ev, vals[order])  # pin of the oracle itself
+    for shape in [(0, 0, 0), (2, 8, 8), (3, 8, 8)]:
+        say("case identity bits=%d shape=%s" % (bits, shape))
+        k, v, o = ms.pairs(dev(keys), dev(vals), m, ms.BucketFn.shift_mask(0, m - 1),
+                           options=ms.Options(*shape))
+        np.testing.assert_array_equal(host(k), ek)
+        np.testing.assert_array_equal(host(v), ev)
+        np.testing.assert_array_equal(host(o), eo)
