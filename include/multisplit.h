@@ -198,7 +198,14 @@ size_t ms_workspace_size(int op, size_t n, uint32_t m, uint32_t num_inst,
  *               bucket j, d_offsets[m] = n (the paper's optional bucket-start
  *               array, Section 3.1, plus its end).
  *   n           0 <= n < 2^32.  n = 0 writes offsets of zero.
- *   m           1 <= m <= 256 buckets.
+ *   m           1 <= m <= 256 buckets, or up to 65536 for SHIFT_MASK and
+ *               DIV buckets: then two stable passes of at most 256 buckets
+ *               run, on the low byte of the bucket id and then on its high
+ *               byte (Section 6, "Performance for more than 256 buckets"),
+ *               and the bucket starts come from one pass over the output.
+ *               SPLITTERS and LEARNED buckets above 256 give
+ *               MS_ERR_UNSUPPORTED; the workspace then also holds one copy
+ *               of the data.
  *   fn          bucket identifier (host pointer to the descriptor).
  */
 ms_status ms_keys(const uint32_t* d_keys_in, uint32_t* d_keys_out,

@@ -43,6 +43,23 @@ scan_rows_kernel(uint32_t* __restrict__ H, uint32_t L0, uint32_t* __restrict__ t
   if (threadIdx.x == 0) totals[blockIdx.x] = carry;
 }
 
+// Bucket starts of a bucket-ordered array: offsets[j] = first index whose
+// bucket is >= j, offsets[m] = n.  Element i writes the starts of the buckets
+// in (f(out[i-1]), f(out[i])], so each of the m + 1 entries is written once.
+// Used after the two passes of a multisplit into more than 256 buckets.
+template <int Kind>
+__global__ void __launch_bounds__(256)
+bucket_starts_kernel(const uint32_t* __restrict__ out, uint32_t n, uint32_t m, BucketParams bp,
+                     uint32_t* __restrict__ offsets) {
+  Bucket<Kind, 8> f(bp, nullptr);
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= n;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t lo = i == 0 ? 0u : f(out[i - 1]) + 1u;
+    const uint32_t hi = i == n ? m : f(out[i]);
+    for (uint32_t j = lo; j <= hi; ++j) offsets[j] = (uint32_t)i;
+  }
+}
+
 // Fill n words with a value (used for empty inputs: offsets of zero).
 __global__ void fill_u32_kernel(uint32_t* p, uint32_t n, uint32_t v) {
   uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;

@@ -192,13 +192,16 @@ struct Bucket<kShiftMask, BITS> {
 // floor(k / d) by a multiply-high and two shifts (Granlund and Montgomery,
 // "Division by invariant integers using multiplication", PLDI 1994, the
 // unsigned N-bit algorithm): t = mulhi(magic, k); q = (t + ((k - t) >> sh1)) >> sh2.
+// `mask` keeps the low digit of the quotient when more than 256 buckets are
+// split in two passes (all ones otherwise).
 template <int BITS>
 struct Bucket<kDiv, BITS> {
-  uint32_t magic, sh1, sh2;
-  __device__ Bucket(const BucketParams& p, const BucketLds*) : magic(p.magic), sh1(p.sh1), sh2(p.sh2) {}
+  uint32_t magic, sh1, sh2, mask;
+  __device__ Bucket(const BucketParams& p, const BucketLds*)
+      : magic(p.magic), sh1(p.sh1), sh2(p.sh2), mask(p.mask) {}
   __device__ __forceinline__ uint32_t operator()(uint32_t k) const {
     uint32_t t = __umulhi(magic, k);
-    return (t + ((k - t) >> sh1)) >> sh2;
+    return ((t + ((k - t) >> sh1)) >> sh2) & mask;
   }
   __device__ __forceinline__ uint32_t misses() const { return 0; }
 };

@@ -33,9 +33,11 @@ struct Shape {
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// Smallest b with 2^b >= m, for any 32-bit m (64-bit shifts: at m > 2^31 the
+// answer is 32, which a 32-bit shift cannot represent).
 uint32_t ceil_log2(uint32_t m) {
   uint32_t b = 0;
-  while ((1u << b) < m) ++b;
+  while ((1ull << b) < (uint64_t)m) ++b;
   return b;
 }
 
@@ -176,13 +178,17 @@ int validate_fn(const ms_bucket_fn* fn, uint32_t m) {
   }
 }
 
-BucketParams make_params(const ms_bucket_fn* fn, uint32_t m, uint64_t* mispredicts) {
+BucketParams make_params(const ms_bucket_fn* fn, uint32_t m, uint64_t* mispredicts,
+                         uint32_t div_mask = 0xFFFFFFFFu) {
   BucketParams bp;
   memset(&bp, 0, sizeof(bp));
   bp.m = m;
   bp.shift = fn->shift;
   bp.mask = fn->mask;
-  if (fn->kind == MS_BUCKET_DIV) div_magic(fn->divisor, &bp.magic, &bp.sh1, &bp.sh2);
+  if (fn->kind == MS_BUCKET_DIV) {
+    div_magic(fn->divisor, &bp.magic, &bp.sh1, &bp.sh2);
+    bp.mask = div_mask;  // the quotient's kept bits (all for a plain delta bucket)
+  }
   bp.splitters = fn->splitters;
   bp.model = fn->model;
   bp.mispredicts = (unsigned long long*)mispredicts;
@@ -304,7 +310,8 @@ BatchWorkspace carve_batch(void* ws, size_t total, uint32_t m, uint32_t num, con
 // The three stages for one multisplit on already validated arguments.
 ms_status run_multisplit(const uint32_t* ki, const uint32_t* vi, uint32_t* ko, uint32_t* vo,
                          uint32_t* offsets, size_t n, uint32_t m, const ms_bucket_fn* fn,
-                         void* ws, const Shape& s, const ms_options* opt, hipStream_t st) {
+                         void* ws, const Shape& s, const ms_options* opt, hipStream_t st,
+                         uint32_t div_mask = 0xFFFFFFFFu) {
   const bool kv = vi != nullptr;
   if (n == 0) {
     if (fill(offsets, m + 1, 0, st) != hipSuccess) return MS_ERR_HIP;
@@ -312,7 +319,7 @@ ms_status run_multisplit(const uint32_t* ki, const uint32_t* vi, uint32_t* ko, u
   }
   Plan p = make_plan(n, m, s, kv);
   Workspace w = carve(ws, p);
-  BucketParams bp = make_params(fn, m, opt ? opt->d_mispredicts : nullptr);
+  BucketParams bp = make_params(fn, m, opt ? opt->d_mispredicts : nullptr, div_mask);
   const int bits = (int)ceil_log2(m);
   if (record(opt, 0, st) != hipSuccess) return MS_ERR_HIP;
   ms::PreArgs pa{ki, p, bp, w.H, s.mode, s.hist, st};
@@ -332,8 +339,9 @@ ms_status run_multisplit(const uint32_t* ki, const uint32_t* vi, uint32_t* ko, u
 }
 
 ms_status check_common(const uint32_t* ki, const uint32_t* vi, const uint32_t* ko,
-                       const uint32_t* vo, size_t n, uint32_t m, bool kv) {
-  if (m < 1 || m > (uint32_t)ms::kMaxBuckets) return MS_ERR_INVALID_ARG;
+                       const uint32_t* vo, size_t n, uint32_t m, bool kv,
+                       uint32_t m_max = ms::kMaxBuckets) {
+  if (m < 1 || m > m_max) return MS_ERR_INVALID_ARG;
   if (n >= 0xFFFFFFFFull) return MS_ERR_INVALID_ARG;
   if (n > 0) {
     if (!ki || !ko) return MS_ERR_INVALID_ARG;
@@ -343,6 +351,112 @@ ms_status check_common(const uint32_t* ki, const uint32_t* vi, const uint32_t* k
     if (kv && (overlaps(vi, vo, bytes) || overlaps(ko, vo, bytes) || overlaps(ki, vo, bytes) ||
                overlaps(vi, ko, bytes)))
       return MS_ERR_INVALID_ARG;
+  }
+  return MS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// More than 256 buckets (Section 6, "Performance for more than 256 buckets":
+// iterated multisplits of at most 256 buckets, as radix sort does).  For
+// shift/mask and delta buckets the bucket id B = f(k) < 2^16 splits into
+// digits lo = B & 255 and hi = B >> 8, each itself a shift/mask or delta
+// bucket function: a stable pass on lo, then a stable pass on hi, leaves the
+// elements ordered by (hi, lo) = B with input order kept inside a bucket.
+// The bucket starts then come from one pass over the output.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kMaxBucketsWide = 1u << 16;
+
+struct WidePasses {
+  ms_bucket_fn lo, hi;
+  uint32_t m_lo, m_hi;
+  uint32_t lo_div_mask;  // delta: the quotient's low byte
+};
+
+WidePasses wide_passes(const ms_bucket_fn* fn, uint32_t m) {
+  WidePasses w;
+  memset(&w, 0, sizeof(w));
+  w.lo = *fn;
+  w.hi = *fn;
+  w.m_lo = 256;
+  w.m_hi = (m - 1) / 256 + 1;
+  w.lo_div_mask = 0xFFFFFFFFu;
+  if (fn->kind == MS_BUCKET_SHIFT_MASK) {
+    w.lo.mask = fn->mask & 255u;
+    if (fn->shift + 8 < 32) {
+      w.hi.shift = fn->shift + 8;
+      w.hi.mask = fn->mask >> 8;
+    } else {  // every id has its high byte zero
+      w.hi.shift = 0;
+      w.hi.mask = 0;
+    }
+  } else {  // delta: floor(floor(k / d) / 256) = floor(k / 256d)
+    w.lo_div_mask = 255u;
+    const uint64_t d2 = (uint64_t)fn->divisor * 256u;
+    if (d2 <= 0xFFFFFFFFull) {
+      w.hi.divisor = (uint32_t)d2;
+    } else {  // k / d < 256 for every key: the high byte is zero
+      w.hi.kind = MS_BUCKET_SHIFT_MASK;
+      w.hi.shift = 0;
+      w.hi.mask = 0;
+    }
+  }
+  return w;
+}
+
+size_t wide_ws_bytes(size_t n, uint32_t m, bool kv, const ms_options* opt) {
+  size_t data = align_up(n * 4, kWsAlign) * (kv ? 2 : 1);
+  size_t best = 0;
+  const uint32_t ms_[2] = {256u, (m - 1) / 256 + 1};
+  const int kinds[2] = {MS_BUCKET_SHIFT_MASK, MS_BUCKET_SPLITTERS};
+  for (uint32_t mm : ms_)
+    for (int kd : kinds) {
+      Shape s;
+      if (resolve_shape(opt, mm, kd, &s) != MS_OK) return 0;
+      size_t b = ms_ws_bytes(make_plan(n, mm, s, kv));
+      if (b > best) best = b;
+    }
+  return data + best;
+}
+
+ms_status run_wide(const uint32_t* ki, const uint32_t* vi, uint32_t* ko, uint32_t* vo,
+                   uint32_t* offsets, size_t n, uint32_t m, const ms_bucket_fn* fn, void* ws,
+                   const ms_options* opt, hipStream_t st) {
+  if (n == 0) return fill(offsets, m + 1, 0, st) == hipSuccess ? MS_OK : MS_ERR_HIP;
+  const bool kv = vi != nullptr;
+  const WidePasses w = wide_passes(fn, m);
+  char* b = (char*)ws;
+  uint32_t* tk = (uint32_t*)b;
+  b += align_up(n * 4, kWsAlign);
+  uint32_t* tv = nullptr;
+  if (kv) {
+    tv = (uint32_t*)b;
+    b += align_up(n * 4, kWsAlign);
+  }
+  Shape s_lo, s_hi;
+  int r = resolve_shape(opt, w.m_lo, w.lo.kind, &s_lo);
+  if (r != MS_OK) return (ms_status)r;
+  r = resolve_shape(opt, w.m_hi, w.hi.kind, &s_hi);
+  if (r != MS_OK) return (ms_status)r;
+  ms_options o;
+  memset(&o, 0, sizeof(o));
+  if (opt) o = *opt;
+  o.stage_events = nullptr;  // stages of the second pass only
+  ms_status e = run_multisplit(ki, vi, tk, tv, nullptr, n, w.m_lo, &w.lo, b, s_lo, &o, st,
+                               w.lo_div_mask);
+  if (e != MS_OK) return e;
+  if (opt) o.stage_events = opt->stage_events;
+  e = run_multisplit(tk, tv, ko, vo, nullptr, n, w.m_hi, &w.hi, b, s_hi, &o, st);
+  if (e != MS_OK) return e;
+  if (offsets) {
+    const BucketParams bp = make_params(fn, m, nullptr);
+    const uint32_t blocks = (uint32_t)((n + 1 + 255) / 256 < 4096 ? (n + 1 + 255) / 256 : 4096);
+    if (fn->kind == MS_BUCKET_SHIFT_MASK)
+      hipLaunchKernelGGL(ms::bucket_starts_kernel<ms::kShiftMask>, dim3(blocks), dim3(256), 0, st,
+                         ko, (uint32_t)n, m, bp, offsets);
+    else
+      hipLaunchKernelGGL(ms::bucket_starts_kernel<ms::kDiv>, dim3(blocks), dim3(256), 0, st, ko,
+                         (uint32_t)n, m, bp, offsets);
+    if (hipGetLastError() != hipSuccess) return MS_ERR_HIP;
   }
   return MS_OK;
 }
@@ -368,6 +482,10 @@ const char* ms_version(void) { return "multisplit-gfx950 0.1"; }
 
 size_t ms_workspace_size(int op, size_t n, uint32_t m, uint32_t num_inst, const ms_options* opt) {
   (void)num_inst;
+  if ((op == MS_OP_KEYS || op == MS_OP_PAIRS) && m > (uint32_t)ms::kMaxBuckets) {
+    if (m > kMaxBucketsWide || n >= 0xFFFFFFFFull) return 0;
+    return wide_ws_bytes(n, m, op == MS_OP_PAIRS, opt);
+  }
   Shape s;  // radix passes use shift/mask buckets
   if (resolve_shape(opt, m, MS_BUCKET_SHIFT_MASK, &s) != MS_OK) return 0;
   switch (op) {
@@ -418,10 +536,17 @@ ms_status ms_pairs(const uint32_t* d_keys_in, const uint32_t* d_vals_in, uint32_
                    const ms_bucket_fn* fn, void* d_ws, size_t ws_bytes, const ms_options* opt,
                    void* stream) {
   bool kv = d_vals_in != nullptr || d_vals_out != nullptr;
-  ms_status rc = check_common(d_keys_in, d_vals_in, d_keys_out, d_vals_out, n, m, kv);
+  ms_status rc = check_common(d_keys_in, d_vals_in, d_keys_out, d_vals_out, n, m, kv,
+                              kMaxBucketsWide);
   if (rc != MS_OK) return rc;
   int fr = validate_fn(fn, m);
   if (fr != MS_OK) return (ms_status)fr;
+  if (m > (uint32_t)ms::kMaxBuckets) {
+    if (fn->kind != MS_BUCKET_SHIFT_MASK && fn->kind != MS_BUCKET_DIV) return MS_ERR_UNSUPPORTED;
+    if (n > 0 && (!d_ws || ws_bytes < wide_ws_bytes(n, m, kv, opt))) return MS_ERR_WORKSPACE;
+    return run_wide(d_keys_in, kv ? d_vals_in : nullptr, d_keys_out, d_vals_out, d_offsets, n, m,
+                    fn, d_ws, opt, (hipStream_t)stream);
+  }
   Shape s;
   int sr = resolve_shape(opt, m, fn->kind, &s);
   if (sr != MS_OK) return (ms_status)sr;

@@ -50,7 +50,7 @@ def test_host_validation_rejects_before_launch(L):
     assert need > 0
     # m out of range
     assert L.ms_keys(ki, ko, None, n, 0, ctypes.byref(fn), ws, need, None, None) == -1
-    assert L.ms_keys(ki, ko, None, n, 257, ctypes.byref(fn), ws, need, None, None) == -1
+    assert L.ms_keys(ki, ko, None, n, 65537, ctypes.byref(fn), ws, need, None, None) == -1
     # null pointers with n > 0, and overlapping in/out
     assert L.ms_keys(None, ko, None, n, 32, ctypes.byref(fn), ws, need, None, None) == -1
     assert L.ms_keys(ki, fake(0x1000000 + 8), None, n, 32, ctypes.byref(fn), ws, need, None,
@@ -122,3 +122,25 @@ def test_default_shape_for_every_reorder_mode(L):
             o = OptionsC(mode, 0, 0, 0, None, None)
             for op in (0, 1, 6):
                 assert L.ms_workspace_size(op, 1 << 20, m, 0, ctypes.byref(o)) > 0, (mode, m, op)
+
+
+def test_more_than_256_buckets_host_checks(L):
+    """m up to 65536 for shift/mask and delta buckets (two passes); range
+    buckets above 256 are unsupported; histogram, radix digits and batched
+    stay at 256."""
+    from paper_1701_01189_amd.binding import BucketFnC
+    ki, ko, ws = fake(0x1000000), fake(0x9000000), fake(0x20000000)
+    n = 1000
+    need = L.ms_workspace_size(0, n, 4096, 0, None)
+    assert need >= 4 * n
+    assert L.ms_workspace_size(1, n, 4096, 0, None) >= 8 * n
+    assert L.ms_workspace_size(0, n, 65537, 0, None) == 0
+    fn = BucketFnC(0, 20, 4095, 0, None, None)
+    assert L.ms_keys(ki, ko, None, n, 65537, ctypes.byref(fn), ws, need, None, None) == -1
+    assert L.ms_keys(ki, ko, None, n, 4096, ctypes.byref(fn), ws, need - 1, None, None) == -2
+    bad = BucketFnC(0, 20, 8191, 0, None, None)
+    assert L.ms_keys(ki, ko, None, n, 4096, ctypes.byref(bad), ws, need, None, None) == -4
+    spl = BucketFnC(2, 0, 0, 0, fake(0x30000000), None)
+    assert L.ms_keys(ki, ko, None, n, 1000, ctypes.byref(spl), ws, 1 << 30, None, None) == -6
+    assert L.ms_histogram(ki, n, 1000, ctypes.byref(fn), fake(0x40000000), ws, need, None,
+                          None) == -1

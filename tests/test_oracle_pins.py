@@ -239,3 +239,24 @@ def test_brute_force_detects_planted_mistake():
     j = int(off[1])  # swap two entries of one bucket: breaks stability only
     ov[j], ov[j + 1] = ov[j + 1], ov[j]
     assert any(ov[p[i]] != vals[i] for i in range(40))
+
+
+@pytest.mark.parametrize("m", [257, 1000, 4096, 65536])
+def test_oracle_more_than_256_buckets_matches_stable_argsort(m):
+    """The oracle's counting sort has no bucket limit: pinned by numpy's
+    stable argsort of the bucket ids (shift/mask and delta buckets)."""
+    n = 20_011
+    keys = inputs.uniform_u32(m, n)
+    vals = inputs.index_values(n)
+    r = (m - 1).bit_length()
+    d = -(-(1 << 32) // m)
+    for kind, kw, ids in ((oracle.SHIFT_MASK, dict(shift=32 - r, mask=(1 << r) - 1),
+                           keys >> np.uint32(32 - r)),
+                          (oracle.DIV, dict(divisor=d), (keys.astype(np.uint64) // d))):
+        mm = 1 << r if kind == oracle.SHIFT_MASK else m
+        k, v, off = oracle.multisplit(keys, mm, kind, vals=vals, **kw)
+        order = np.argsort(ids, kind="stable")
+        np.testing.assert_array_equal(v, vals[order])
+        np.testing.assert_array_equal(k, keys[order])
+        np.testing.assert_array_equal(np.diff(off.astype(np.int64)),
+                                      np.bincount(ids.astype(np.int64), minlength=mm))
