@@ -44,6 +44,7 @@ def parse():
     ap.add_argument("--waves", type=int, default=0)
     ap.add_argument("--items", type=int, default=0)
     ap.add_argument("--chunks", type=int, default=0)
+    ap.add_argument("--claim", type=int, default=0, help="batched: work items per queue claim")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--cold-reps", type=int, default=10,
@@ -297,8 +298,9 @@ def bench_batched(args, num, m, shift, seed, dev):
     dv = torch.from_numpy(vals.view(np.int32)).to(dev)
     ds = torch.from_numpy(seg.astype(np.int64)).to(dev)
     fn = ms.BucketFn.shift_mask(shift, m - 1)
-    if args.reorder or args.waves or args.items:
-        opt = ms.Options(waves_per_block=args.waves, items_per_lane=args.items)
+    if args.reorder or args.waves or args.items or args.claim:
+        opt = ms.Options(waves_per_block=args.waves, items_per_lane=args.items,
+                         batch_claim=args.claim)
         tune = {"source": "command line"}
     else:
         opt, tune = tuning.tuned_options(ms.OP_BATCHED, dk, dv, m, fn=fn, seg=ds)
