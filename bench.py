@@ -90,14 +90,18 @@ def copy_ceiling(dev, reps=20, n=1 << 28):
 
 def cold_steps(step, reps, dev):
     """Each call timed alone (HIP events on the call's stream) after a 1 GiB
-    scratch write that evicts the 256 MB Infinity Cache and the L2s (the
-    write itself is outside the timed region).  Returns per-call ms."""
+    scratch buffer is written and then read back, outside the timed region:
+    the write evicts the 256 MB Infinity Cache and the L2s, and the read
+    evicts the write's own dirty lines, so the timed call neither finds its
+    data in a cache nor pays for someone else's write-back.  Returns
+    per-call ms."""
     import torch
     scratch = torch.empty(1 << 28, dtype=torch.int32, device=dev)
     hev = HipEvents(2 * reps)
     out = []
     for i in range(reps):
         scratch.fill_(i)
+        scratch.sum()
         torch.cuda.synchronize()
         hev.record(2 * i)
         step(None)
