@@ -102,10 +102,6 @@ prescan_kernel(const uint32_t* __restrict__ keys, Plan plan, BucketParams bp,
     for (uint32_t i = threadIdx.x; i < NB * kWave; i += WPB * kWave) s_lane[i] = 0u;
   stage_bucket_tables<Kind>(bp, &tables);
   __syncthreads();
-  // A chunk's count of bucket b goes to its column of H.
-  auto emit = [&](uint32_t b, uint32_t v) {
-    H[b * plan.L0 + blockIdx.x * GPB + (wave_id() / WPG)] = v;
-  };
   auto lane_count = [&](uint32_t b, uint32_t lane) {
     __hip_atomic_fetch_add(&s_lane[b * kWave + lane], 1u, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -117,6 +113,8 @@ prescan_kernel(const uint32_t* __restrict__ keys, Plan plan, BucketParams bp,
   const uint32_t w = wave_id();
   const uint32_t g = w / WPG, wg = w % WPG;
   const uint32_t c = blockIdx.x * GPB + g;
+  // The chunk's count of bucket b goes to its column of H.
+  auto emit = [&](uint32_t b, uint32_t v) { H[b * plan.L0 + c] = v; };
   uint32_t cnt[MB];
 #pragma unroll
   for (int t = 0; t < MB; ++t) cnt[t] = 0;
@@ -333,8 +331,8 @@ __device__ __forceinline__ void tile_rank_reorder_write(const BF& bf, uint32_t (
 //     tile_base + (wg*NW + j)*64 + l -- so (wg, j, l) is input order;
 //  2. per window: match mask of the lane's bucket (Algorithm 3), rank among
 //     lower lanes, and a per-wavefront running count per bucket kept in LDS
-//     (the highest lane of each bucket publishes the new count): the first
-//     and second terms of Eq. (4);
+//     (every lane of a bucket stores the same new count): the first and
+//     second terms of Eq. (4);
 //  3. one exclusive scan over the bucket-major table [bucket][wavefront] of
 //     those counts gives, for wavefront wg and bucket b, the number of tile
 //     elements in buckets < b plus those of bucket b in earlier wavefronts --
