@@ -12,7 +12,8 @@ Reported: Gpairs/s of the whole call; the roofline of the dominant kernel
 written once), timed with HIP events on the stream the kernels run on; and
 the CPU oracle timed on the host cores.
 
-Other workloads (--workload): keys_2e20_m8, keys_2e28_m<m>, pairs_2e28_m<m>,
+Other workloads (--workload): keys_2e20_m8, keys_2e28_m<m>, pairs_2e28_m<m>
+(m up to 65536; above 256 two stable passes over 8-bit digits of the bucket),
 radix_pairs_2e28, radix_keys_2e28, hist_2e<k>_m<m> and histrange_2e<k>_m<m>
 (device-wide histograms, even or range bins), and range_2e27_m256: n = 2^27 lognormal
 (mu 20, sigma 2) keys saturated to 32 bits (seed 103), 256 range buckets at
