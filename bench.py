@@ -579,7 +579,9 @@ def main():
         (ms.OP_PAIRS if kv else ms.OP_KEYS)
     ws = torch.empty(max(256, ms.workspace_size(op, n, 256 if radix else m, 0, opt)), dtype=torch.uint8,
                      device=dev)
-    fn = ms.BucketFn.shift_mask(shift, m - 1)
+    # powers of two: shift/mask; other m: delta buckets floor(k / ceil(2^32 / m))
+    pow2 = m & (m - 1) == 0
+    fn = ms.BucketFn.shift_mask(shift, m - 1) if pow2 else ms.BucketFn.div(-(-(1 << 32) // m))
 
     def step(o):
         if radix:
@@ -677,7 +679,8 @@ def main():
         "graph_value": round(units / (graph_ms * 1e-3) / 1e9, 3),
         "config": {"workload": args.workload, "n": n, "m": m,
                    "bucket": ("radix 4 x 8-bit digits" if radix else
-                              "identity (keys < m)" if ident else "shift_mask"),
+                              "identity (keys < m)" if ident else
+                              "shift_mask" if pow2 else "delta ceil(2^32/m)"),
                    "shift": shift, "kv": kv, "seed": seed,
                    "reorder": args.reorder, "waves_per_block": args.waves,
                    "items_per_lane": args.items},

@@ -45,7 +45,7 @@ extern "C" {
 
 typedef enum {
   MS_OK = 0,
-  MS_ERR_INVALID_ARG = -1, /* bad size, null pointer, m out of [1,256], ...   */
+  MS_ERR_INVALID_ARG = -1, /* bad size, null pointer, m out of range, ...        */
   MS_ERR_WORKSPACE = -2,   /* ws_bytes smaller than ms_workspace_size()      */
   MS_ERR_HIP = -3,         /* a HIP runtime call or kernel launch failed     */
   MS_ERR_BUCKET_RANGE = -4,/* bucket function can produce ids >= m           */

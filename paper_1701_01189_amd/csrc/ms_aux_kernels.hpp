@@ -44,20 +44,31 @@ scan_rows_kernel(uint32_t* __restrict__ H, uint32_t L0, uint32_t* __restrict__ t
 }
 
 // Bucket starts of a bucket-ordered array: offsets[j] = first index whose
-// bucket is >= j, offsets[m] = n.  Element i writes the starts of the buckets
-// in (f(out[i-1]), f(out[i])], so each of the m + 1 entries is written once.
+// bucket is >= j (n if none), for j in [0, m].  One lane per boundary runs a
+// lower-bound binary search over the whole array: m + 1 searches of
+// ceil(log2(n + 1)) probes each instead of a pass over all n elements, and
+// the first probes of every search hit the same few lines, which stay in L2.
 // Used after the two passes of a multisplit into more than 256 buckets.
 template <int Kind>
 __global__ void __launch_bounds__(256)
 bucket_starts_kernel(const uint32_t* __restrict__ out, uint32_t n, uint32_t m, BucketParams bp,
                      uint32_t* __restrict__ offsets) {
   Bucket<Kind, 8> f(bp, nullptr);
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= n;
-       i += (uint64_t)gridDim.x * blockDim.x) {
-    const uint32_t lo = i == 0 ? 0u : f(out[i - 1]) + 1u;
-    const uint32_t hi = i == n ? m : f(out[i]);
-    for (uint32_t j = lo; j <= hi; ++j) offsets[j] = (uint32_t)i;
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j > m) return;
+  // Invariant: every index below lo has a bucket < j, every index at or past
+  // lo + len has a bucket >= j, and lo + len <= n, so each probe is in range.
+  uint32_t lo = 0, len = n;
+  while (len > 0) {
+    const uint32_t half = len >> 1;
+    if (f(out[lo + half]) < j) {
+      lo += half + 1;
+      len -= half + 1;
+    } else {
+      len = half;
+    }
   }
+  offsets[j] = lo;
 }
 
 // Fill n words with a value (used for empty inputs: offsets of zero).

@@ -449,7 +449,7 @@ ms_status run_wide(const uint32_t* ki, const uint32_t* vi, uint32_t* ko, uint32_
   if (e != MS_OK) return e;
   if (offsets) {
     const BucketParams bp = make_params(fn, m, nullptr);
-    const uint32_t blocks = (uint32_t)((n + 1 + 255) / 256 < 4096 ? (n + 1 + 255) / 256 : 4096);
+    const uint32_t blocks = (m + 1 + 255) / 256;  // one lane per bucket start
     if (fn->kind == MS_BUCKET_SHIFT_MASK)
       hipLaunchKernelGGL(ms::bucket_starts_kernel<ms::kShiftMask>, dim3(blocks), dim3(256), 0, st,
                          ko, (uint32_t)n, m, bp, offsets);
