@@ -17,7 +17,8 @@ Other workloads (--workload): keys_2e20_m8, keys_2e28_m<m>, pairs_2e28_m<m>
 radix_pairs_2e28, radix_keys_2e28, hist_2e<k>_m<m> and histrange_2e<k>_m<m>
 (device-wide histograms, even or range bins), and range_2e27_m256: n = 2^27 lognormal
 (mu 20, sigma 2) keys saturated to 32 bits (seed 103), 256 range buckets at
-quantiles of a 2^16-key sample (seed 1031); the learned identifier (fit on the
+quantiles of a 2^16-key sample (seed 1031); sssp_rmat_2e20[_d<delta>]: shortest
+paths on an R-MAT graph (Section 7.2); the learned identifier (fit on the
 GPU from 2^20 keys, seed 1032) is timed against the binary search over the
 same splitters, and `value` is the learned rate.
 """
@@ -145,6 +146,10 @@ def workload(name):
         return "range", 1 << 27, 256, 0, 103
     if name == "copy_2e28":
         return "copy", 1 << 28, 1, 0, 7
+    if name.startswith("sssp_rmat_2e20"):
+        # sssp_rmat_2e20 (delta 100) or sssp_rmat_2e20_d<delta>
+        delta = int(name.split("_d")[1]) if "_d" in name else 100
+        return "sssp", 20, 4_800_000, delta, 106
     if name == "batched_4096_m64":
         return "batched", 4096, 64, 8, 104
     if name.startswith("hist_") or name.startswith("histrange_"):
@@ -440,6 +445,84 @@ def bench_hist(args, kind, n, m, shift, seed, dev):
     print(json.dumps(line), flush=True)
 
 
+def bench_sssp(args, scale, n_edges, delta, seed, dev):
+    """Delta-stepping shortest paths with multisplit bucketing (Section 7.2)
+    on the R-MAT graph of the paper's evaluation: 2^scale vertices, n_edges
+    undirected edges drawn with (a, b, c, d) = (0.5, 0.1, 0.1, 0.3), each
+    stored in both directions, integer weights uniform in [0, 1000], source
+    vertex 0, 10 buckets.  One step = one complete ms_sssp call.  The rate is
+    the paper's MTEPS: stored (directed) edges over the call's time."""
+    import numpy as np
+    import torch
+
+    from paper_1701_01189_amd import binding as ms
+    from paper_1701_01189_amd import inputs
+    row, col, wt = inputs.rmat_graph(seed, scale, n_edges)
+    ne = len(col)
+    r = torch.from_numpy(row.astype(np.int64)).to(dev)
+    c = torch.from_numpy(col.view(np.int32)).to(dev)
+    w = torch.from_numpy(wt.view(np.int32)).to(dev)
+    dist = torch.empty(len(row) - 1, dtype=torch.int32, device=dev)
+    ws = torch.empty(ms.sssp_workspace_size(len(row) - 1, ne, 10), dtype=torch.uint8, device=dev)
+    stats = {}
+
+    def step(ev):
+        if ev is not None:
+            ev.record(0)
+        _, st = ms.sssp(r, c, w, 0, delta=delta, num_buckets=10, dist=dist, ws=ws)
+        if ev is not None:
+            ev.record(1)
+        stats.update(st)
+
+    for _ in range(args.warmup):
+        step(None)
+    torch.cuda.synchronize()
+    ev = HipEvents(2)
+    times = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(ev)
+        torch.cuda.synchronize()
+        times.append(ev.ms(0, 1))
+    wall = (time.perf_counter() - t0) / args.steps * 1e3
+    ev.close()
+    t = sum(times) / len(times)
+    # Algorithmic bytes of a run: each pending entry is multisplit as a pair
+    # (20 B: key read by the pre-scan, pair read and written by the
+    # post-scan) and filtered (12 B: pair and its vertex's distance); each
+    # relaxed edge reads its target and weight and updates a distance (16 B);
+    # each improvement appends a pair (8 B).
+    byts = 32 * stats["items_split"] + 16 * stats["edges_relaxed"] + 8 * stats["pushes"]
+    gbps = byts / (t * 1e-3) / 1e9
+    line = {
+        "metric": METRIC, "value": round(ne / (t * 1e-3) / 1e6, 1), "unit": "MTEPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(t, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "graph": "rmat", "scale": scale,
+                   "vertices": len(row) - 1, "edges_stored": ne, "delta": delta, "buckets": 10,
+                   "source": 0, "seed": seed},
+        "wall_ms_per_step": round(wall, 4),
+        "sssp": stats,
+        "roofline": {"bound": "hbm", "kernel": "whole call", "achieved": round(gbps, 1),
+                     "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(gbps / HBM_PEAK_GBPS, 4),
+                     "traffic": None, "bytes_per_run": byts},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            oracle.sssp(row, col, wt, 0)
+            reps += 1
+            el = time.perf_counter() - t0
+            if el > args.cpu_seconds or reps >= 20:
+                break
+        line["cpu_baseline"] = {"value": round(ne * reps / el / 1e6, 2), "unit": "MTEPS",
+                                "cores": 1, "kind": "oracle", "cpu_model": cpu_model(),
+                                "sample": "the full graph, %d Dijkstra runs" % reps}
+    print(json.dumps(line), flush=True)
+
+
 def bench_copy(args, n, dev):
     """Streaming copy of n words (the measured HBM ceiling, and the known
     byte count that scales the FETCH_SIZE / WRITE_SIZE counters)."""
@@ -558,6 +641,8 @@ def main():
         return bench_copy(args, n, dev)
     if kind == "batched":
         return bench_batched(args, n, m, shift, seed, dev)
+    if kind == "sssp":
+        return bench_sssp(args, n, m, shift, seed, dev)
     if kind in ("hist", "histrange"):
         return bench_hist(args, kind, n, m, shift, seed, dev)
     ident = kind.endswith("_ident")

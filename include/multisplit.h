@@ -316,6 +316,51 @@ ms_status ms_autotune(int op, const uint32_t* d_keys_in, const uint32_t* d_vals_
 ms_status ms_copy_u32(uint32_t* d_dst, const uint32_t* d_src, size_t n,
                       void* stream);
 
+/*
+ * Single-source shortest paths by delta-stepping whose work frontier is
+ * bucketed with the stable multisplit (Section 7.2, Multisplit-SSSP: the
+ * Bucketing strategy with its radix sort replaced by a multisplit).
+ *
+ * Graph: directed, CSR on the device -- d_row[nv + 1] uint64 edge offsets
+ * (d_row[0] = 0, non-decreasing, d_row[nv] = ne), d_col[ne] target vertices
+ * (< nv; an edge past the last vertex makes the call return
+ * MS_ERR_INVALID_ARG after it has run), d_wt[ne] non-negative integer
+ * weights.  Paths are summed in 32 bits saturating at 0xFFFFFFFE, so the
+ * caller keeps every shortest path below that.
+ *
+ * Output: d_dist[nv], the least total weight of a path from `source`
+ * (0xFFFFFFFF where unreachable).  The distances do not depend on `delta`
+ * (bucket width, >= 1) or `num_buckets` (B in [2, 256]: B - 1 buckets of
+ * width delta above a moving base plus one open-ended bucket); they set how
+ * much work a round does and how many rounds there are.
+ *
+ * Each round multisplits the pending (distance, vertex) pairs into the B
+ * buckets (splitter buckets), relaxes every out-edge of the lowest occupied
+ * bucket's vertices on the GPU and appends each improvement to the pending
+ * list; see ms_sssp.hip for the steps.  The call synchronises `stream` once
+ * per round (the pending count sizes the next multisplit) and returns when
+ * nothing is pending; not capture-safe.  The workspace (caller owned, size
+ * from ms_sssp_workspace_size, at least nv + ne pending entries) is
+ * clobbered.  `stats` (host, nullable) receives the round counts.
+ * Errors: MS_ERR_INVALID_ARG (null pointer, nv = 0, source >= nv, delta =
+ * 0, B out of range, nv + ne >= 2^32 - 1, a bad edge), MS_ERR_WORKSPACE,
+ * MS_ERR_HIP, MS_ERR_TIMEOUT (more rounds than the algorithm can need).
+ */
+typedef struct {
+  uint64_t rounds;         /* multisplit rounds                             */
+  uint64_t items_split;    /* pending entries multisplit, summed over rounds */
+  uint64_t edges_relaxed;  /* out-edges relaxed, summed over rounds         */
+  uint64_t pushes;         /* improvements appended to the pending list      */
+  uint64_t max_pending;    /* largest pending list                           */
+} ms_sssp_stats;
+
+size_t ms_sssp_workspace_size(uint32_t nv, uint64_t ne, uint32_t num_buckets);
+
+ms_status ms_sssp(const uint64_t* d_row, const uint32_t* d_col, const uint32_t* d_wt,
+                  uint32_t nv, uint64_t ne, uint32_t source, uint32_t delta,
+                  uint32_t num_buckets, uint32_t* d_dist, void* d_ws, size_t ws_bytes,
+                  ms_sssp_stats* stats, void* stream);
+
 /* Version string of the library build. */
 const char* ms_version(void);
 

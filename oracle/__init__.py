@@ -7,7 +7,8 @@ shares no code with the GPU path (it has its own C++ source, built with g++).
 Each function restates a definition from the paper (Ashkiani et al., "GPU
 Multisplit: an extended study of a parallel algorithm"): the stable multisplit
 of Section 3.1 / Eq. (1), the bucket identifiers of Section 6, the radix sort
-of Section 7.1.  See ``oracle.cpp`` for the per-function citations.
+of Section 7.1, and the shortest-path distances that the delta-stepping of
+Section 7.2 computes (Dijkstra's algorithm).  See ``oracle.cpp`` for the per-function citations.
 
 Bucket kinds use the oracle's own numbering:
     SHIFT_MASK (0): (k >> p0) & p1
@@ -73,6 +74,8 @@ def _load():
     lib.or_learned_fit.restype = None
     lib.or_learned_bucket_ids.argtypes = [PF, P32, u32, P32, u64, P32, P64]
     lib.or_learned_bucket_ids.restype = None
+    lib.or_sssp.argtypes = [P64, P32, P32, u32, u32, P32]
+    lib.or_sssp.restype = i32
     _lib = lib
     return lib
 
@@ -189,3 +192,20 @@ def learned_bucket_ids(model, splitters, m, keys):
     _load().or_learned_bucket_ids(_fp(model), _u32p(spl), m, _u32p(keys), len(keys),
                                   _u32p(out), ctypes.byref(miss))
     return out, int(miss.value)
+
+
+INF = 0xFFFFFFFF
+
+
+def sssp(row, col, wt, src):
+    """Shortest-path distances from src over a CSR graph (row: nv+1 offsets,
+    col/wt: one entry per directed edge); INF where unreachable."""
+    row = np.ascontiguousarray(row, dtype=np.uint64)
+    col, wt = _c32(col), _c32(wt)
+    nv = len(row) - 1
+    dist = np.empty(nv, dtype=np.uint32)
+    rc = _load().or_sssp(row.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), _u32p(col),
+                         _u32p(wt), nv, int(src), _u32p(dist))
+    if rc != 0:
+        raise ValueError("a shortest path does not fit in 32 bits")
+    return dist

@@ -25,6 +25,10 @@
 //     its own; offsets are relative to the segment start.
 //   * device-wide histogram -- Section 7.3: the number of keys per bucket,
 //     h_j = #{i : f(u_i) = j} (the same h_j as in Eq. 1), counted in one pass.
+//   * single-source shortest paths -- Section 7.2 uses multisplit to bucket
+//     the work frontier of delta-stepping; whatever the bucketing, the result
+//     is the shortest-path distance of every vertex, which is unique.  The
+//     oracle is Dijkstra's algorithm (a binary heap with lazy deletion).
 //   * learned bucket identifier -- a two-stage piecewise-linear model of the
 //     bucket as a function of the key (an even split of the key range into
 //     leaves, then a least-squares line per leaf) fit in double precision,
@@ -39,7 +43,9 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <functional>
 #include <numeric>
+#include <queue>
 #include <vector>
 
 namespace {
@@ -271,6 +277,41 @@ void or_learned_bucket_ids(const float* model, const uint32_t* spl, uint32_t m,
     if (out) out[i] = exact;
   }
   if (mispredicts) *mispredicts = miss;
+}
+
+// Single-source shortest paths on a directed graph in CSR form (row offsets
+// nv + 1, column and weight per edge): dist[v] = the least total weight of a
+// path from src to v, 0xFFFFFFFF if v is unreachable.  Dijkstra's algorithm:
+// pop the closest unsettled vertex, relax its out-edges.  Distances are
+// accumulated in 64 bits; a graph whose shortest path reaches 0xFFFFFFFF
+// returns -1.  Section 7.2 (the problem it solves; the paper's delta-stepping
+// must produce the same distances).
+int or_sssp(const uint64_t* row, const uint32_t* col, const uint32_t* wt, uint32_t nv,
+            uint32_t src, uint32_t* dist) {
+  const uint64_t kInf = ~0ull;
+  std::vector<uint64_t> d(nv, kInf);
+  typedef std::pair<uint64_t, uint32_t> Item;  // (distance, vertex)
+  std::priority_queue<Item, std::vector<Item>, std::greater<Item>> heap;
+  d[src] = 0;
+  heap.push(Item(0, src));
+  while (!heap.empty()) {
+    const Item top = heap.top();
+    heap.pop();
+    const uint32_t u = top.second;
+    if (top.first != d[u]) continue;  // a stale entry: u was settled closer
+    for (uint64_t e = row[u]; e < row[u + 1]; ++e) {
+      const uint64_t nd = d[u] + wt[e];
+      if (nd < d[col[e]]) {
+        d[col[e]] = nd;
+        heap.push(Item(nd, col[e]));
+      }
+    }
+  }
+  for (uint32_t v = 0; v < nv; ++v) {
+    if (d[v] != kInf && d[v] >= 0xFFFFFFFFull) return -1;
+    dist[v] = d[v] == kInf ? 0xFFFFFFFFu : (uint32_t)d[v];
+  }
+  return 0;
 }
 
 }  // extern "C"

@@ -38,6 +38,12 @@ class BucketFnC(ctypes.Structure):
                 ("model", ctypes.c_void_p)]
 
 
+class SsspStatsC(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_uint64), ("items_split", ctypes.c_uint64),
+                ("edges_relaxed", ctypes.c_uint64), ("pushes", ctypes.c_uint64),
+                ("max_pending", ctypes.c_uint64)]
+
+
 class OptionsC(ctypes.Structure):
     _fields_ = [("reorder", ctypes.c_int32), ("waves_per_block", ctypes.c_int32),
                 ("items_per_lane", ctypes.c_int32), ("max_chunks", ctypes.c_int32),
@@ -49,7 +55,7 @@ class OptionsC(ctypes.Structure):
 _lib = None
 SYMBOLS = ["ms_status_str", "ms_version", "ms_workspace_size", "ms_keys", "ms_pairs",
            "ms_radix_sort", "ms_batched", "ms_batched_status", "ms_learned_fit", "ms_copy_u32",
-           "ms_autotune"]
+           "ms_autotune", "ms_sssp", "ms_sssp_workspace_size"]
 
 
 def lib():
@@ -92,6 +98,12 @@ def lib():
     L.ms_learned_fit.restype = i32
     L.ms_copy_u32.argtypes = [vp, vp, sz, vp]
     L.ms_copy_u32.restype = i32
+    u64 = ctypes.c_uint64
+    L.ms_sssp_workspace_size.argtypes = [u32, u64, u32]
+    L.ms_sssp_workspace_size.restype = sz
+    L.ms_sssp.argtypes = [vp, vp, vp, u32, u64, u32, u32, u32, vp, vp, sz,
+                          ctypes.POINTER(SsspStatsC), vp]
+    L.ms_sssp.restype = i32
     _lib = L
     return L
 
@@ -365,3 +377,36 @@ def copy_u32(dst, src, stream=None):
     rc = lib().ms_copy_u32(_u32(dst, "dst"), _u32(src, "src"), src.numel(), _stream(stream))
     _check(rc, "ms_copy_u32")
     return dst
+
+
+INF = 0xFFFFFFFF
+
+
+def sssp_workspace_size(nv, ne, num_buckets=10):
+    return int(lib().ms_sssp_workspace_size(nv, ne, num_buckets))
+
+
+def sssp(row, col, wt, source, delta=100, num_buckets=10, dist=None, ws=None, stream=None):
+    """Shortest-path distances from `source` by delta-stepping with multisplit
+    bucketing.  row: int64 tensor of nv + 1 CSR offsets; col, wt: 32-bit
+    tensors of ne targets and weights (all on the GPU).  Returns (dist, stats):
+    dist an int32 tensor holding the uint32 distances (INF where unreachable),
+    stats a dict of round counts."""
+    import torch
+    if row.dtype != torch.int64:
+        raise ValueError("row must hold 64-bit offsets")
+    nv, ne = row.numel() - 1, col.numel()
+    if wt.numel() != ne:
+        raise ValueError("col and wt differ in length")
+    if dist is None:
+        dist = torch.empty(max(nv, 1), dtype=torch.int32, device=row.device)
+    if ws is None:
+        need = sssp_workspace_size(nv, ne, num_buckets)
+        ws = torch.empty(max(need, 256), dtype=torch.uint8, device=row.device)
+    st = SsspStatsC()
+    rc = lib().ms_sssp(_ptr(row), _u32(col, "col") if ne else None,
+                       _u32(wt, "wt") if ne else None, nv, ne, source, delta, num_buckets,
+                       _u32(dist, "dist"), _ptr(ws), ws.numel(), ctypes.byref(st),
+                       _stream(stream))
+    _check(rc, "ms_sssp")
+    return dist, {k: int(getattr(st, k)) for k, _ in SsspStatsC._fields_}

@@ -1,0 +1,431 @@
+// Single-source shortest paths by delta-stepping with multisplit bucketing
+// (Section 7.2, "Multisplit-SSSP": the Bucketing strategy with its radix
+// sort replaced by a multisplit).
+//
+// The work frontier is a list of (tentative distance, vertex) pairs.  Each
+// round:
+//   1. a stable multisplit of the pairs (key = distance) into B range
+//      buckets of width Delta above a moving base: bucket j holds distances
+//      in [base + j*Delta, base + (j+1)*Delta), the last bucket everything
+//      from base + (B-1)*Delta up (the splitter bucket kind of Section 6);
+//   2. the lowest non-empty bucket is the near set; the buckets above it
+//      stay pending, minus entries whose vertex has since been reached by a
+//      shorter path (stale entries);
+//   3. every out-edge of every near vertex is relaxed with an atomic
+//      minimum on the distance array; each relaxation that lowers a
+//      distance appends (new distance, vertex) to the pending list.
+// The base moves up to the near bucket's lower edge; when only the last
+// bucket holds entries, the base jumps to the least pending distance and the
+// round relaxes nothing.  The loop ends when no entry is pending.  The
+// result is the shortest-path distance of every vertex (unique), whatever
+// Delta, B or the order of the atomic updates.
+//
+// Work balance: relaxation is edge parallel.  The near vertices' degrees are
+// scanned (a reduce-then-scan over 2048-entry blocks) and each edge finds
+// its vertex by binary search in the scanned degrees, so high-degree and
+// low-degree vertices cost the same per edge.
+//
+// One host synchronisation per round reads the pending count, which sizes
+// the next multisplit.  Everything else (the near bucket, the base, the
+// splitters of the next round) stays on the device.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+#include <string.h>
+
+#include "multisplit.h"
+#include "ms_device.hpp"
+
+namespace {
+
+using ms::count_below;
+using ms::kWave;
+using ms::lane_id;
+using ms::popc64;
+
+constexpr uint32_t kInf = 0xFFFFFFFFu;      // unreachable
+constexpr uint32_t kDistMax = 0xFFFFFFFEu;  // longest representable path
+constexpr int kThreads = 256;
+constexpr int kPer = 8;
+constexpr uint32_t kBlockItems = kThreads * kPer;  // items per degree block
+constexpr uint32_t kExpandBlocks = 2048;           // 8 workgroups per CU
+constexpr size_t kAlign = 256;
+
+// Loop state in device memory (one aligned slot of the workspace).
+struct State {
+  uint32_t count;      // entries appended to the pending list this round
+  uint32_t overflow;   // an append found the pending list full
+  uint32_t bad_edge;   // an edge pointed past the last vertex
+  uint32_t base;       // lower edge of bucket 0
+  uint32_t jump;       // only the last bucket was occupied: no relaxation
+  uint32_t near_lo, near_hi;  // near bucket in the multisplit output
+  uint32_t far_lo;            // first pending entry above the near bucket
+  uint32_t edges;             // edges to relax this round
+  uint32_t far_min;           // least valid pending distance (jump rounds)
+  uint32_t pad[2];
+  unsigned long long relaxed;  // edges relaxed, all rounds
+  unsigned long long pushes;   // entries appended by relaxations, all rounds
+};
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+__device__ __forceinline__ uint32_t sat_add(uint32_t a, uint32_t b) {
+  const uint64_t s = (uint64_t)a + b;
+  return s > kDistMax ? kDistMax : (uint32_t)s;
+}
+
+// Splitters of the next round: base + (i+1)*Delta, saturated.
+__device__ __forceinline__ void write_splitters(uint32_t* spl, uint32_t nb, uint32_t base,
+                                                uint32_t delta) {
+  for (uint32_t i = threadIdx.x; i + 1 < nb; i += blockDim.x) {
+    const uint64_t s = (uint64_t)base + (uint64_t)(i + 1) * delta;
+    spl[i] = s > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)s;
+  }
+}
+
+// Appends (d, v) for every lane with `put`; one atomic per wavefront.  An
+// entry past the list's capacity is dropped and flags the overflow.  Every
+// lane of the wavefront must call it.
+__device__ __forceinline__ void wave_append(bool put, uint32_t d, uint32_t v, State* st,
+                                            uint32_t* pk, uint32_t* pv, uint32_t cap,
+                                            bool count_push) {
+  const uint64_t mask = ms::ballot(put);
+  if (mask == 0) return;
+  const uint32_t leader = (uint32_t)__builtin_ctzll(mask);
+  const uint32_t lane = lane_id();
+  uint32_t base = 0;
+  if (lane == leader) {
+    base = atomicAdd(&st->count, popc64(mask));
+    if (count_push) atomicAdd(&st->pushes, (unsigned long long)popc64(mask));
+  }
+  base = __shfl(base, (int)leader, kWave);
+  if (put) {
+    const uint32_t idx = base + count_below(mask);
+    if (idx < cap) {
+      pk[idx] = d;
+      pv[idx] = v;
+    } else {
+      st->overflow = 1u;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kThreads)
+sssp_init_kernel(uint32_t* __restrict__ dist, uint32_t nv, uint32_t src, uint32_t* pk,
+                 uint32_t* pv, State* st, uint32_t* spl, uint32_t nb, uint32_t delta) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    dist[i] = i == src ? 0u : kInf;
+  if (blockIdx.x == 0) {
+    if (threadIdx.x == 0) {
+      pk[0] = 0u;
+      pv[0] = src;
+      st->count = 1u;
+      st->overflow = 0u;
+      st->bad_edge = 0u;
+      st->base = 0u;
+      st->jump = 0u;
+      st->near_lo = st->near_hi = st->far_lo = 0u;
+      st->edges = 0u;
+      st->far_min = kInf;
+      st->relaxed = 0ull;
+      st->pushes = 0ull;
+    }
+    write_splitters(spl, nb, 0u, delta);
+  }
+}
+
+// Picks the near bucket from the multisplit's bucket starts (one wavefront).
+__global__ void sssp_choose_kernel(const uint32_t* __restrict__ offsets, uint32_t n, uint32_t nb,
+                                   uint32_t delta, State* st) {
+  if (threadIdx.x != 0) return;
+  uint32_t j = 0;
+  while (j + 1 < nb && offsets[j + 1] == offsets[j]) ++j;  // first occupied bucket
+  const uint32_t lo = offsets[j];
+  if (j + 1 == nb) {
+    // Only the last (open-ended) bucket is occupied: keep everything pending
+    // and jump the base to the least valid distance found by the filter.
+    st->jump = 1u;
+    st->near_lo = st->near_hi = lo;
+    st->far_lo = lo;
+  } else {
+    const uint64_t b = (uint64_t)st->base + (uint64_t)j * delta;
+    st->base = b > kDistMax ? kDistMax : (uint32_t)b;
+    st->jump = 0u;
+    st->near_lo = lo;
+    st->near_hi = offsets[j + 1];
+    st->far_lo = offsets[j + 1];
+  }
+  (void)n;
+  st->count = 0u;
+  st->far_min = kInf;
+}
+
+// Per block of 2048 multisplit-output entries: keeps the valid pending
+// entries above the near bucket (appended to the next pending list), and
+// sums the degrees of the valid near entries (written per entry, and per
+// block into partial[]).  An entry is valid while its distance equals the
+// vertex's current distance.
+__global__ void __launch_bounds__(kThreads)
+sssp_filter_kernel(const uint32_t* __restrict__ ok, const uint32_t* __restrict__ ov, uint32_t n,
+                   const uint64_t* __restrict__ row, const uint32_t* __restrict__ dist, State* st,
+                   uint32_t* pk, uint32_t* pv, uint32_t cap, uint32_t* __restrict__ deg,
+                   uint32_t* __restrict__ partial) {
+  __shared__ uint32_t s_sum[kThreads / kWave];
+  const uint32_t near_lo = st->near_lo, near_hi = st->near_hi, far_lo = st->far_lo;
+  const bool jump = st->jump != 0u;
+  const uint32_t b0 = blockIdx.x * kBlockItems;
+  uint32_t sum = 0, fmin = kInf;
+#pragma unroll
+  for (int e = 0; e < kPer; ++e) {
+    const uint32_t i = b0 + (uint32_t)e * kThreads + threadIdx.x;
+    bool keep = false;
+    uint32_t d = 0, v = 0;
+    if (i < n) {
+      d = ok[i];
+      v = ov[i];
+      const bool valid = dist[v] == d;
+      if (i >= far_lo) {
+        keep = valid;
+        if (valid && d < fmin) fmin = d;
+      } else if (i >= near_lo && i < near_hi) {
+        const uint32_t g = valid ? (uint32_t)(row[v + 1] - row[v]) : 0u;
+        deg[i] = g;
+        sum += g;
+      }
+    }
+    wave_append(keep, d, v, st, pk, pv, cap, false);
+  }
+  // block sum of near degrees
+  uint32_t inc = ms::wave_inclusive_scan(sum, lane_id());
+  const uint32_t w = threadIdx.x / kWave;
+  if (lane_id() == kWave - 1) s_sum[w] = inc;
+  if (jump) {
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+      const uint32_t t = __shfl_xor(fmin, o, kWave);
+      fmin = t < fmin ? t : fmin;
+    }
+    if (lane_id() == 0 && fmin != kInf) atomicMin(&st->far_min, fmin);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t t = 0;
+    for (int k = 0; k < kThreads / kWave; ++k) t += s_sum[k];
+    partial[blockIdx.x] = t;
+  }
+}
+
+// Exclusive scan of the per-block degree sums (one workgroup); the total is
+// this round's edge count.  Then moves the base (jump rounds) and writes the
+// next round's splitters.
+__global__ void __launch_bounds__(kThreads)
+sssp_scan_kernel(uint32_t* __restrict__ partial, uint32_t nblocks, State* st, uint32_t* spl,
+                 uint32_t nb, uint32_t delta) {
+  __shared__ uint32_t s_w[kThreads / kWave];
+  __shared__ uint32_t s_carry, s_base;
+  const uint32_t lane = lane_id(), w = threadIdx.x / kWave;
+  if (threadIdx.x == 0) s_carry = 0;
+  __syncthreads();
+  for (uint32_t b = 0; b < nblocks; b += kThreads) {
+    const uint32_t i = b + threadIdx.x;
+    const uint32_t v = i < nblocks ? partial[i] : 0u;
+    const uint32_t inc = ms::wave_inclusive_scan(v, lane);
+    if (lane == kWave - 1) s_w[w] = inc;
+    __syncthreads();
+    uint32_t before = s_carry, all = 0;
+    for (uint32_t k = 0; k < kThreads / kWave; ++k) {
+      before += k < w ? s_w[k] : 0u;
+      all += s_w[k];
+    }
+    if (i < nblocks) partial[i] = before + inc - v;
+    __syncthreads();
+    if (threadIdx.x == 0) s_carry += all;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    st->edges = s_carry;
+    st->relaxed += s_carry;
+    uint32_t base = st->base;
+    if (st->jump && st->far_min != kInf) base = st->far_min;
+    st->base = base;
+    s_base = base;
+  }
+  __syncthreads();
+  write_splitters(spl, nb, s_base, delta);
+}
+
+// Scanned degrees: deg[i] becomes the index of entry i's first edge among
+// the round's edges (near entries only; a thread scans 8 consecutive).
+__global__ void __launch_bounds__(kThreads)
+sssp_edge_offsets_kernel(uint32_t n, const State* st, uint32_t* __restrict__ deg,
+                         const uint32_t* __restrict__ partial) {
+  __shared__ uint32_t s_w[kThreads / kWave];
+  const uint32_t near_lo = st->near_lo, near_hi = st->near_hi;
+  const uint32_t i0 = blockIdx.x * kBlockItems + threadIdx.x * kPer;
+  uint32_t g[kPer], sum = 0;
+#pragma unroll
+  for (int e = 0; e < kPer; ++e) {
+    const uint32_t i = i0 + (uint32_t)e;
+    g[e] = (i < n && i >= near_lo && i < near_hi) ? deg[i] : 0u;
+    sum += g[e];
+  }
+  const uint32_t lane = lane_id(), w = threadIdx.x / kWave;
+  const uint32_t inc = ms::wave_inclusive_scan(sum, lane);
+  if (lane == kWave - 1) s_w[w] = inc;
+  __syncthreads();
+  uint32_t run = partial[blockIdx.x] + inc - sum;
+  for (uint32_t k = 0; k < w; ++k) run += s_w[k];
+#pragma unroll
+  for (int e = 0; e < kPer; ++e) {
+    const uint32_t i = i0 + (uint32_t)e;
+    if (i < n && i >= near_lo && i < near_hi) deg[i] = run;
+    run += g[e];
+  }
+}
+
+// Edge-parallel relaxation of the near bucket.  Edge e of the round belongs
+// to the last near entry whose first-edge index is <= e (entries with no
+// edges share their successor's index and are passed over).
+__global__ void __launch_bounds__(kThreads)
+sssp_relax_kernel(const uint32_t* __restrict__ ok, const uint32_t* __restrict__ ov,
+                  const uint64_t* __restrict__ row, const uint32_t* __restrict__ col,
+                  const uint32_t* __restrict__ wt, uint32_t nv, uint32_t* dist, State* st,
+                  const uint32_t* __restrict__ eoff, uint32_t* pk, uint32_t* pv, uint32_t cap) {
+  const uint64_t edges = st->edges;
+  const uint32_t near_lo = st->near_lo, near_hi = st->near_hi;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  // Every lane runs the same number of trips so the appends stay wave wide.
+  const uint64_t wave_first = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x - lane_id();
+  for (uint64_t eb = wave_first; eb < edges; eb += stride) {
+    const uint64_t e64 = eb + lane_id();
+    const uint32_t e = (uint32_t)e64;  // < edges <= 2^32 - 1 when used
+    bool put = false;
+    uint32_t nd = 0, u = 0;
+    if (e64 < edges) {
+      uint32_t lo = near_lo, len = near_hi - near_lo;
+      while (len > 0) {  // first entry whose first-edge index exceeds e
+        const uint32_t half = len >> 1;
+        if (eoff[lo + half] <= e) {
+          lo += half + 1;
+          len -= half + 1;
+        } else {
+          len = half;
+        }
+      }
+      const uint32_t item = lo - 1;  // eoff[near_lo] == 0 <= e, so lo > near_lo
+      const uint32_t v = ov[item];
+      const uint64_t ge = row[v] + (e - eoff[item]);
+      u = col[ge];
+      if (u < nv) {
+        nd = sat_add(ok[item], wt[ge]);
+        put = atomicMin(&dist[u], nd) > nd;
+      } else {
+        st->bad_edge = 1u;
+      }
+    }
+    wave_append(put, nd, u, st, pk, pv, cap, true);
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t ms_sssp_workspace_size(uint32_t nv, uint64_t ne, uint32_t num_buckets) {
+  if (nv == 0 || num_buckets < 2 || num_buckets > 256) return 0;
+  const uint64_t cap = (uint64_t)nv + ne;
+  if (cap >= 0xFFFFFFFFull) return 0;
+  const size_t ms_ws = ms_workspace_size(MS_OP_PAIRS, (size_t)cap, num_buckets, 0, nullptr);
+  if (ms_ws == 0) return 0;
+  const size_t nblk = (cap + kBlockItems - 1) / kBlockItems;
+  return align_up(sizeof(State)) + align_up(256 * 4) + align_up(257 * 4) +
+         5 * align_up(cap * 4) + align_up(nblk * 4) + align_up(ms_ws);
+}
+
+ms_status ms_sssp(const uint64_t* d_row, const uint32_t* d_col, const uint32_t* d_wt,
+                  uint32_t nv, uint64_t ne, uint32_t source, uint32_t delta,
+                  uint32_t num_buckets, uint32_t* d_dist, void* d_ws, size_t ws_bytes,
+                  ms_sssp_stats* stats, void* stream) {
+  if (!d_row || !d_dist || nv == 0 || source >= nv || delta == 0) return MS_ERR_INVALID_ARG;
+  if (ne > 0 && (!d_col || !d_wt)) return MS_ERR_INVALID_ARG;
+  if (num_buckets < 2 || num_buckets > 256) return MS_ERR_INVALID_ARG;
+  const uint64_t cap64 = (uint64_t)nv + ne;
+  if (cap64 >= 0xFFFFFFFFull) return MS_ERR_INVALID_ARG;
+  const size_t need = ms_sssp_workspace_size(nv, ne, num_buckets);
+  if (!d_ws || ws_bytes < need) return MS_ERR_WORKSPACE;
+  const uint32_t cap = (uint32_t)cap64;
+  const uint32_t nb = num_buckets;
+  hipStream_t s = (hipStream_t)stream;
+
+  char* p = (char*)d_ws;
+  State* st = (State*)p;
+  p += align_up(sizeof(State));
+  uint32_t* spl = (uint32_t*)p;
+  p += align_up(256 * 4);
+  uint32_t* offsets = (uint32_t*)p;
+  p += align_up(257 * 4);
+  uint32_t* pk = (uint32_t*)p;
+  p += align_up((size_t)cap * 4);
+  uint32_t* pv = (uint32_t*)p;
+  p += align_up((size_t)cap * 4);
+  uint32_t* ok = (uint32_t*)p;
+  p += align_up((size_t)cap * 4);
+  uint32_t* ov = (uint32_t*)p;
+  p += align_up((size_t)cap * 4);
+  uint32_t* deg = (uint32_t*)p;
+  p += align_up((size_t)cap * 4);
+  uint32_t* partial = (uint32_t*)p;
+  p += align_up(((size_t)cap + kBlockItems - 1) / kBlockItems * 4);
+  void* ms_ws = p;
+  const size_t ms_ws_bytes = ws_bytes - (size_t)(p - (char*)d_ws);
+
+  const uint64_t want = ((uint64_t)nv + kThreads - 1) / kThreads;
+  const uint32_t init_blocks = want < 4096 ? (uint32_t)want : 4096u;
+  hipLaunchKernelGGL(sssp_init_kernel, dim3(init_blocks), dim3(kThreads), 0, s, d_dist, nv,
+                     source, pk, pv, st, spl, nb, delta);
+  if (hipGetLastError() != hipSuccess) return MS_ERR_HIP;
+
+  ms_sssp_stats acc;
+  memset(&acc, 0, sizeof(acc));
+  const ms_bucket_fn fn = {MS_BUCKET_SPLITTERS, 0u, 0u, 0u, spl, nullptr};
+  // Each round either lowers some distance, shrinks the pending list or
+  // jumps the base; this bound only guards against a broken invariant.
+  const uint64_t max_rounds = 4 * cap64 + 64;
+  uint32_t n = 1;
+  while (n > 0) {
+    if (acc.rounds >= max_rounds) return MS_ERR_TIMEOUT;
+    ms_status rc = ms_pairs(pk, pv, ok, ov, offsets, n, nb, &fn, ms_ws, ms_ws_bytes, nullptr, s);
+    if (rc != MS_OK) return rc;
+    const uint32_t nblocks = (uint32_t)(((uint64_t)n + kBlockItems - 1) / kBlockItems);
+    hipLaunchKernelGGL(sssp_choose_kernel, dim3(1), dim3(kWave), 0, s, offsets, n, nb, delta, st);
+    hipLaunchKernelGGL(sssp_filter_kernel, dim3(nblocks), dim3(kThreads), 0, s, ok, ov, n, d_row,
+                       d_dist, st, pk, pv, cap, deg, partial);
+    hipLaunchKernelGGL(sssp_scan_kernel, dim3(1), dim3(kThreads), 0, s, partial, nblocks, st, spl,
+                       nb, delta);
+    hipLaunchKernelGGL(sssp_edge_offsets_kernel, dim3(nblocks), dim3(kThreads), 0, s, n, st, deg,
+                       partial);
+    hipLaunchKernelGGL(sssp_relax_kernel, dim3(kExpandBlocks), dim3(kThreads), 0, s, ok, ov,
+                       d_row, d_col, d_wt, nv, d_dist, st, deg, pk, pv, cap);
+    if (hipGetLastError() != hipSuccess) return MS_ERR_HIP;
+    uint32_t h[3];
+    if (hipMemcpyAsync(h, st, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return MS_ERR_HIP;
+    if (h[1]) return MS_ERR_WORKSPACE;  // cannot happen: the list holds nv + ne
+    if (h[2]) return MS_ERR_INVALID_ARG;  // an edge names a vertex >= nv
+    acc.rounds += 1;
+    acc.items_split += n;
+    if (n > acc.max_pending) acc.max_pending = n;
+    n = h[0];
+  }
+  State hs;
+  if (hipMemcpyAsync(&hs, st, sizeof(hs), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return MS_ERR_HIP;
+  acc.edges_relaxed = hs.relaxed;
+  acc.pushes = hs.pushes;
+  if (stats) *stats = acc;
+  return MS_OK;
+}
+
+}  // extern "C"

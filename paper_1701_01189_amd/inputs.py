@@ -161,3 +161,38 @@ def batched_pairs(seed: int, sizes: np.ndarray):
         vals[pos:pos + s] = np.arange(s, dtype=np.uint32)
         pos += s
     return keys, vals
+
+
+def rmat_graph(seed: int, scale: int, n_edges: int, a: float = 0.5, b: float = 0.1,
+               c: float = 0.1, max_weight: int = 1000):
+    """Undirected R-MAT graph (Chakrabarti, Zhan and Faloutsos, SDM 2004) in
+    directed CSR form, each edge stored in both directions.
+
+    Edge e picks its endpoints by ``scale`` recursive quadrant choices on the
+    2^scale x 2^scale adjacency matrix, most significant bit first, with draw
+    ``l * n_edges + e`` of the stream at level l: top-left with probability
+    a, top-right b, bottom-left c, bottom-right 1 - a - b - c.  Its weight is
+    floor(u * (max_weight + 1)) for the draw ``scale * n_edges + e``, an
+    integer uniform in [0, max_weight].  Self loops are dropped; repeated
+    edges are kept.  Rows list their edges in generation order (forward
+    directions first, then reverse ones).
+
+    Returns (row uint64[nv + 1], col uint32[ne], wt uint32[ne]), nv = 2^scale.
+    """
+    nv = 1 << scale
+    src = np.zeros(n_edges, dtype=np.int64)
+    dst = np.zeros(n_edges, dtype=np.int64)
+    for level in range(scale):
+        r = uniform_f64(seed, n_edges, start=level * n_edges)
+        src = 2 * src + (r >= a + b)
+        dst = 2 * dst + (((r >= a) & (r < a + b)) | (r >= a + b + c))
+    w = np.floor(uniform_f64(seed, n_edges, start=scale * n_edges) * (max_weight + 1))
+    w = w.astype(np.int64)
+    keep = src != dst
+    s = np.concatenate([src[keep], dst[keep]])
+    d = np.concatenate([dst[keep], src[keep]])
+    ww = np.concatenate([w[keep], w[keep]])
+    order = np.argsort(s, kind="stable")
+    row = np.zeros(nv + 1, dtype=np.uint64)
+    np.cumsum(np.bincount(s, minlength=nv), out=row[1:])
+    return row, d[order].astype(np.uint32), ww[order].astype(np.uint32)

@@ -144,3 +144,28 @@ def test_more_than_256_buckets_host_checks(L):
     assert L.ms_keys(ki, ko, None, n, 1000, ctypes.byref(spl), ws, 1 << 30, None, None) == -6
     assert L.ms_histogram(ki, n, 1000, ctypes.byref(fn), fake(0x40000000), ws, need, None,
                           None) == -1
+
+
+def test_sssp_host_checks(L):
+    from paper_1701_01189_amd.binding import SsspStatsC
+    sz = L.ms_sssp_workspace_size
+    assert sz(1000, 5000, 10) > 0
+    assert sz(0, 5, 10) == 0 and sz(5, 5, 1) == 0 and sz(5, 5, 257) == 0
+    assert sz(1 << 31, 1 << 31, 10) == 0  # nv + ne must stay below 2^32 - 1
+    row, col, wt, dist = fake(0x1000000), fake(0x2000000), fake(0x3000000), fake(0x4000000)
+    ws = fake(0x20000000)
+    need = sz(100, 400, 10)
+    st = SsspStatsC()
+
+    def call(nv=100, ne=400, src=0, delta=50, nb=10, r=row, c=col, w=wt, d=dist, wsb=need):
+        return L.ms_sssp(r, c, w, nv, ne, src, delta, nb, d, ws, wsb, ctypes.byref(st), None)
+
+    invalid, workspace = -1, -2
+    assert call(nv=0) == invalid
+    assert call(src=100) == invalid
+    assert call(delta=0) == invalid
+    assert call(nb=1) == invalid and call(nb=257) == invalid
+    assert call(r=None) == invalid and call(d=None) == invalid
+    assert call(c=None) == invalid and call(w=None) == invalid
+    assert call(nv=1 << 31, ne=1 << 31) == invalid
+    assert call(wsb=need - 1) == workspace

@@ -1,0 +1,122 @@
+"""GPU parity of the delta-stepping shortest paths with multisplit bucketing
+(Section 7.2) against the oracle's Dijkstra: the distances are unique, so
+they are compared bit for bit, for every vertex, whatever Delta and the
+bucket count.  Graphs: random directed graphs of several densities and
+weight ranges (zero weights and unreachable vertices included), paths, the
+R-MAT graph of the paper's evaluation at full size (2^20 vertices, 4.8 M
+undirected edges stored both ways) and at smaller scales.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1701_01189_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def dev_graph(row, col, wt):
+    r = torch.from_numpy(row.astype(np.int64)).cuda()
+    c = torch.from_numpy(np.ascontiguousarray(col, dtype=np.uint32).view(np.int32)).cuda()
+    w = torch.from_numpy(np.ascontiguousarray(wt, dtype=np.uint32).view(np.int32)).cuda()
+    return r, c, w
+
+
+def host(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+def csr(nv, src, dst, w):
+    src, dst, w = (np.asarray(a, dtype=np.int64) for a in (src, dst, w))
+    order = np.argsort(src, kind="stable")
+    row = np.zeros(nv + 1, dtype=np.uint64)
+    np.cumsum(np.bincount(src, minlength=nv), out=row[1:])
+    return row, dst[order].astype(np.uint32), w[order].astype(np.uint32)
+
+
+def random_graph(seed, nv, ne, wmax):
+    rng = np.random.default_rng(seed)
+    return csr(nv, rng.integers(0, nv, ne), rng.integers(0, nv, ne),
+               rng.integers(0, wmax + 1, ne))
+
+
+CASES = [  # (seed, nv, ne, max weight, source, delta, buckets)
+    (1, 1, 0, 0, 0, 1, 2),
+    (2, 2, 1, 5, 0, 1, 2),
+    (3, 100, 0, 10, 7, 10, 10),
+    (4, 500, 3000, 1000, 0, 100, 10),
+    (5, 500, 3000, 1000, 499, 1, 2),
+    (6, 2000, 4000, 0, 3, 50, 10),          # zero weights: reachability
+    (7, 3000, 60000, 1000, 11, 1000000, 10),  # one bucket holds everything
+    (8, 10000, 30000, 100000, 5, 7, 256),
+    (9, 50000, 400000, 1000, 123, 200, 16),
+    (10, 4096, 200000, 3, 0, 1, 3),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[str(c[0]) for c in CASES])
+def test_sssp_random_graphs_vs_oracle(case):
+    from paper_1701_01189_amd import binding as ms
+    seed, nv, ne, wmax, src, delta, nb = case
+    row, col, wt = random_graph(seed, nv, ne, wmax)
+    say("case sssp random seed=%d nv=%d ne=%d delta=%d buckets=%d" % (seed, nv, ne, delta, nb))
+    exp = oracle.sssp(row, col, wt, src)
+    dist, st = ms.sssp(*dev_graph(row, col, wt), src, delta=delta, num_buckets=nb)
+    np.testing.assert_array_equal(host(dist), exp)
+    assert st["rounds"] >= 1 and st["items_split"] >= st["rounds"]
+    assert st["max_pending"] <= nv + ne
+
+
+def test_sssp_long_path_and_jumps():
+    from paper_1701_01189_amd import binding as ms
+    # a 3000-vertex path with weights far above delta * buckets: every other
+    # round only the open-ended bucket is occupied and the base jumps
+    nv = 3000
+    w = (np.arange(nv - 1, dtype=np.int64) % 7 + 1) * 10000
+    row, col, wt = csr(nv, np.arange(nv - 1), np.arange(1, nv), w)
+    say("case sssp path nv=%d" % nv)
+    dist, st = ms.sssp(*dev_graph(row, col, wt), 0, delta=100, num_buckets=4)
+    np.testing.assert_array_equal(host(dist), oracle.sssp(row, col, wt, 0))
+    assert st["edges_relaxed"] == nv - 1 and st["pushes"] == nv - 1
+
+
+@pytest.mark.parametrize("delta", [1, 100, 400])
+def test_sssp_rmat_scale16_vs_oracle(delta):
+    from paper_1701_01189_amd import binding as ms
+    row, col, wt = inputs.rmat_graph(60, 16, 300_000)
+    say("case sssp rmat scale=16 delta=%d" % delta)
+    exp = oracle.sssp(row, col, wt, 0)
+    dist, st = ms.sssp(*dev_graph(row, col, wt), 0, delta=delta)
+    np.testing.assert_array_equal(host(dist), exp)
+    reached_edges = int(np.diff(row.astype(np.int64))[exp != oracle.INF].sum())
+    assert st["edges_relaxed"] >= reached_edges  # every reached vertex relaxed at least once
+
+
+def test_sssp_rmat_full_size_vs_oracle():
+    from paper_1701_01189_amd import binding as ms
+    row, col, wt = inputs.rmat_graph(106, 20, 4_800_000)
+    say("case sssp rmat scale=20 edges=%d" % len(col))
+    exp = oracle.sssp(row, col, wt, 0)
+    g = dev_graph(row, col, wt)
+    for src, delta in ((0, 100), (12345, 200)):
+        if src != 0:
+            exp = oracle.sssp(row, col, wt, src)
+        dist, st = ms.sssp(*g, src, delta=delta)
+        np.testing.assert_array_equal(host(dist), exp)
+        say("  rounds=%d relaxed=%d pushes=%d" % (st["rounds"], st["edges_relaxed"], st["pushes"]))
+
+
+def test_sssp_bad_edge_is_reported():
+    from paper_1701_01189_amd import binding as ms
+    row, col, wt = csr(4, [0, 1, 2], [1, 2, 3], [1, 1, 1])
+    col = col.copy()
+    col[1] = 4  # names a vertex past the last one; the kernel skips it
+    say("case sssp bad edge")
+    with pytest.raises(ms.MultisplitError):
+        ms.sssp(*dev_graph(row, col, wt), 0, delta=1)
