@@ -46,26 +46,47 @@ using ms::popc64;
 constexpr uint32_t kInf = 0xFFFFFFFFu;      // unreachable
 constexpr uint32_t kDistMax = 0xFFFFFFFEu;  // longest representable path
 constexpr int kThreads = 256;
-constexpr int kPer = 8;
-constexpr uint32_t kBlockItems = kThreads * kPer;  // items per degree block
-constexpr uint32_t kExpandBlocks = 2048;           // 8 workgroups per CU
+constexpr int kPer = 4;
+constexpr uint32_t kBlockItems = kThreads * kPer;  // entries per filter workgroup
+constexpr int kEdgePer = 8;
+constexpr uint32_t kChunk = kThreads * kEdgePer;   // edges per relaxation chunk
+constexpr uint32_t kExpandBlocks = 1024;           // 4 workgroups per CU
 constexpr size_t kAlign = 256;
 
-// Loop state in device memory (one aligned slot of the workspace).
+// Loop state in device memory (one aligned slot of the workspace).  The
+// append counter and the least pending distance are kept per round parity:
+// a round's single-workgroup scan kernel clears the next round's pair, so no
+// launch is spent on resetting them.
 struct State {
-  uint32_t count;      // entries appended to the pending list this round
-  uint32_t overflow;   // an append found the pending list full
-  uint32_t bad_edge;   // an edge pointed past the last vertex
-  uint32_t base;       // lower edge of bucket 0
-  uint32_t jump;       // only the last bucket was occupied: no relaxation
-  uint32_t near_lo, near_hi;  // near bucket in the multisplit output
-  uint32_t far_lo;            // first pending entry above the near bucket
-  uint32_t edges;             // edges to relax this round
-  uint32_t far_min;           // least valid pending distance (jump rounds)
-  uint32_t pad[2];
+  uint32_t count[2];     // entries appended to the pending list, by round parity
+  uint32_t overflow;     // an append found the pending list full
+  uint32_t bad_edge;     // an edge pointed past the last vertex
+  uint32_t base;         // lower edge of bucket 0
+  uint32_t edges;        // edges to relax this round
+  uint32_t far_min[2];   // least valid pending distance, by round parity
   unsigned long long relaxed;  // edges relaxed, all rounds
   unsigned long long pushes;   // entries appended by relaxations, all rounds
 };
+
+// The round's near bucket, read from the multisplit's bucket starts: the
+// first occupied bucket j.  When only the last (open-ended) bucket is
+// occupied the round is a jump: nothing is near, everything stays pending
+// and the base moves to the least pending distance.  Wavefront uniform.
+struct Near {
+  uint32_t j, lo, hi;  // near entries [lo, hi); pending entries above from hi
+  bool jump;
+};
+
+__device__ __forceinline__ Near near_bucket(const uint32_t* offsets, uint32_t nb) {
+  Near r;
+  uint32_t j = 0;
+  while (j + 1 < nb && offsets[j + 1] == offsets[j]) ++j;
+  r.j = j;
+  r.lo = offsets[j];
+  r.jump = j + 1 == nb;
+  r.hi = r.jump ? r.lo : offsets[j + 1];
+  return r;
+}
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -83,30 +104,42 @@ __device__ __forceinline__ void write_splitters(uint32_t* spl, uint32_t nb, uint
   }
 }
 
-// Appends (d, v) for every lane with `put`; one atomic per wavefront.  An
-// entry past the list's capacity is dropped and flags the overflow.  Every
-// lane of the wavefront must call it.
-__device__ __forceinline__ void wave_append(bool put, uint32_t d, uint32_t v, State* st,
-                                            uint32_t* pk, uint32_t* pv, uint32_t cap,
-                                            bool count_push) {
-  const uint64_t mask = ms::ballot(put);
-  if (mask == 0) return;
-  const uint32_t leader = (uint32_t)__builtin_ctzll(mask);
-  const uint32_t lane = lane_id();
-  uint32_t base = 0;
-  if (lane == leader) {
-    base = atomicAdd(&st->count, popc64(mask));
-    if (count_push) atomicAdd(&st->pushes, (unsigned long long)popc64(mask));
-  }
-  base = __shfl(base, (int)leader, kWave);
-  if (put) {
-    const uint32_t idx = base + count_below(mask);
-    if (idx < cap) {
-      pk[idx] = d;
-      pv[idx] = v;
-    } else {
-      st->overflow = 1u;
+// Reserves `mine` consecutive pending-list slots for every thread of the
+// workgroup with one atomic, and returns this thread's first slot (threads
+// in order).  Every thread of the workgroup must call it.
+__device__ __forceinline__ uint32_t group_reserve(uint32_t mine, uint32_t* counter,
+                                                  unsigned long long* pushes, uint32_t* s_w,
+                                                  uint32_t* s_base) {
+  const uint32_t lane = lane_id(), w = threadIdx.x / kWave;
+  const uint32_t inc = ms::wave_inclusive_scan(mine, lane);
+  if (lane == kWave - 1) s_w[w] = inc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t total = 0;
+    for (int k = 0; k < kThreads / kWave; ++k) total += s_w[k];
+    uint32_t base = 0;
+    if (total) {
+      base = atomicAdd(counter, total);
+      if (pushes) atomicAdd(pushes, (unsigned long long)total);
     }
+    *s_base = base;
+  }
+  __syncthreads();
+  uint32_t first = *s_base + inc - mine;
+  for (uint32_t k = 0; k < w; ++k) first += s_w[k];
+  __syncthreads();  // s_w and s_base may be reused right after
+  return first;
+}
+
+// Stores one reserved entry; an entry past the list's capacity is dropped
+// and flags the overflow.
+__device__ __forceinline__ void put_entry(uint32_t idx, uint32_t d, uint32_t v, State* st,
+                                          uint32_t* pk, uint32_t* pv, uint32_t cap) {
+  if (idx < cap) {
+    pk[idx] = d;
+    pv[idx] = v;
+  } else {
+    st->overflow = 1u;
   }
 }
 
@@ -120,14 +153,12 @@ sssp_init_kernel(uint32_t* __restrict__ dist, uint32_t nv, uint32_t src, uint32_
     if (threadIdx.x == 0) {
       pk[0] = 0u;
       pv[0] = src;
-      st->count = 1u;
+      st->count[0] = st->count[1] = 0u;
       st->overflow = 0u;
       st->bad_edge = 0u;
       st->base = 0u;
-      st->jump = 0u;
-      st->near_lo = st->near_hi = st->far_lo = 0u;
       st->edges = 0u;
-      st->far_min = kInf;
+      st->far_min[0] = st->far_min[1] = kInf;
       st->relaxed = 0ull;
       st->pushes = 0ull;
     }
@@ -135,109 +166,104 @@ sssp_init_kernel(uint32_t* __restrict__ dist, uint32_t nv, uint32_t src, uint32_
   }
 }
 
-// Picks the near bucket from the multisplit's bucket starts (one wavefront).
-__global__ void sssp_choose_kernel(const uint32_t* __restrict__ offsets, uint32_t n, uint32_t nb,
-                                   uint32_t delta, State* st) {
-  if (threadIdx.x != 0) return;
-  uint32_t j = 0;
-  while (j + 1 < nb && offsets[j + 1] == offsets[j]) ++j;  // first occupied bucket
-  const uint32_t lo = offsets[j];
-  if (j + 1 == nb) {
-    // Only the last (open-ended) bucket is occupied: keep everything pending
-    // and jump the base to the least valid distance found by the filter.
-    st->jump = 1u;
-    st->near_lo = st->near_hi = lo;
-    st->far_lo = lo;
-  } else {
-    const uint64_t b = (uint64_t)st->base + (uint64_t)j * delta;
-    st->base = b > kDistMax ? kDistMax : (uint32_t)b;
-    st->jump = 0u;
-    st->near_lo = lo;
-    st->near_hi = offsets[j + 1];
-    st->far_lo = offsets[j + 1];
-  }
-  (void)n;
-  st->count = 0u;
-  st->far_min = kInf;
-}
-
-// Per block of 2048 multisplit-output entries: keeps the valid pending
+// Per workgroup of 1024 multisplit-output entries: keeps the valid pending
 // entries above the near bucket (appended to the next pending list), and
 // sums the degrees of the valid near entries (written per entry, and per
-// block into partial[]).  An entry is valid while its distance equals the
-// vertex's current distance.
+// workgroup into partial[]).  An entry is valid while its distance equals
+// the vertex's current distance.
 __global__ void __launch_bounds__(kThreads)
 sssp_filter_kernel(const uint32_t* __restrict__ ok, const uint32_t* __restrict__ ov, uint32_t n,
                    const uint64_t* __restrict__ row, const uint32_t* __restrict__ dist, State* st,
                    uint32_t* pk, uint32_t* pv, uint32_t cap, uint32_t* __restrict__ deg,
-                   uint32_t* __restrict__ partial) {
-  __shared__ uint32_t s_sum[kThreads / kWave];
-  const uint32_t near_lo = st->near_lo, near_hi = st->near_hi, far_lo = st->far_lo;
-  const bool jump = st->jump != 0u;
+                   uint32_t* __restrict__ partial, const uint32_t* __restrict__ offsets,
+                   uint32_t nb, uint32_t par) {
+  __shared__ uint32_t s_w[kThreads / kWave];
+  __shared__ uint32_t s_base;
+  const Near nr = near_bucket(offsets, nb);
+  const uint32_t near_lo = nr.lo, near_hi = nr.hi, far_lo = nr.hi;
+  const bool jump = nr.jump;
   const uint32_t b0 = blockIdx.x * kBlockItems;
-  uint32_t sum = 0, fmin = kInf;
+  uint32_t d[kPer], v[kPer];
 #pragma unroll
   for (int e = 0; e < kPer; ++e) {
     const uint32_t i = b0 + (uint32_t)e * kThreads + threadIdx.x;
-    bool keep = false;
-    uint32_t d = 0, v = 0;
-    if (i < n) {
-      d = ok[i];
-      v = ov[i];
-      const bool valid = dist[v] == d;
-      if (i >= far_lo) {
-        keep = valid;
-        if (valid && d < fmin) fmin = d;
-      } else if (i >= near_lo && i < near_hi) {
-        const uint32_t g = valid ? (uint32_t)(row[v + 1] - row[v]) : 0u;
-        deg[i] = g;
-        sum += g;
-      }
-    }
-    wave_append(keep, d, v, st, pk, pv, cap, false);
+    d[e] = i < n ? ok[i] : kInf;
+    v[e] = i < n ? ov[i] : 0u;
   }
-  // block sum of near degrees
-  uint32_t inc = ms::wave_inclusive_scan(sum, lane_id());
-  const uint32_t w = threadIdx.x / kWave;
-  if (lane_id() == kWave - 1) s_sum[w] = inc;
+  uint32_t dv[kPer];
+#pragma unroll
+  for (int e = 0; e < kPer; ++e) dv[e] = dist[v[e]];  // v < nv on every lane
+  uint32_t sum = 0, fmin = kInf, nkeep = 0;
+  bool keep[kPer];
+#pragma unroll
+  for (int e = 0; e < kPer; ++e) {
+    const uint32_t i = b0 + (uint32_t)e * kThreads + threadIdx.x;
+    const bool valid = i < n && dv[e] == d[e];
+    keep[e] = valid && i >= far_lo;
+    nkeep += keep[e] ? 1u : 0u;
+    if (keep[e] && d[e] < fmin) fmin = d[e];
+    if (i < n && i >= near_lo && i < near_hi) {
+      const uint32_t g = valid ? (uint32_t)(row[v[e] + 1] - row[v[e]]) : 0u;
+      deg[i] = g;
+      sum += g;
+    }
+  }
+  uint32_t slot = group_reserve(nkeep, &st->count[par], nullptr, s_w, &s_base);
+#pragma unroll
+  for (int e = 0; e < kPer; ++e)
+    if (keep[e]) put_entry(slot++, d[e], v[e], st, pk, pv, cap);
   if (jump) {
     for (int o = kWave / 2; o > 0; o >>= 1) {
       const uint32_t t = __shfl_xor(fmin, o, kWave);
       fmin = t < fmin ? t : fmin;
     }
-    if (lane_id() == 0 && fmin != kInf) atomicMin(&st->far_min, fmin);
+    if (lane_id() == 0 && fmin != kInf) atomicMin(&st->far_min[par], fmin);
   }
+  // workgroup sum of near degrees
+  const uint32_t inc = ms::wave_inclusive_scan(sum, lane_id());
+  if (lane_id() == kWave - 1) s_w[threadIdx.x / kWave] = inc;
   __syncthreads();
   if (threadIdx.x == 0) {
     uint32_t t = 0;
-    for (int k = 0; k < kThreads / kWave; ++k) t += s_sum[k];
+    for (int k = 0; k < kThreads / kWave; ++k) t += s_w[k];
     partial[blockIdx.x] = t;
   }
 }
 
 // Exclusive scan of the per-block degree sums (one workgroup); the total is
-// this round's edge count.  Then moves the base (jump rounds) and writes the
-// next round's splitters.
+// this round's edge count.  Then moves the base (up to the near bucket's
+// lower edge, or to the least pending distance in a jump round) and writes
+// the next round's splitters.
 __global__ void __launch_bounds__(kThreads)
 sssp_scan_kernel(uint32_t* __restrict__ partial, uint32_t nblocks, State* st, uint32_t* spl,
-                 uint32_t nb, uint32_t delta) {
+                 uint32_t nb, uint32_t delta, const uint32_t* __restrict__ offsets, uint32_t par) {
   __shared__ uint32_t s_w[kThreads / kWave];
   __shared__ uint32_t s_carry, s_base;
   const uint32_t lane = lane_id(), w = threadIdx.x / kWave;
   if (threadIdx.x == 0) s_carry = 0;
   __syncthreads();
-  for (uint32_t b = 0; b < nblocks; b += kThreads) {
-    const uint32_t i = b + threadIdx.x;
-    const uint32_t v = i < nblocks ? partial[i] : 0u;
-    const uint32_t inc = ms::wave_inclusive_scan(v, lane);
+  // 4 consecutive sums per thread per pass
+  for (uint32_t b = 0; b < nblocks; b += 4 * kThreads) {
+    const uint32_t i0 = b + 4 * threadIdx.x;
+    uint32_t v[4], t = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      v[k] = i0 + k < nblocks ? partial[i0 + k] : 0u;
+      t += v[k];
+    }
+    const uint32_t inc = ms::wave_inclusive_scan(t, lane);
     if (lane == kWave - 1) s_w[w] = inc;
     __syncthreads();
-    uint32_t before = s_carry, all = 0;
+    uint32_t before = s_carry + inc - t, all = 0;
     for (uint32_t k = 0; k < kThreads / kWave; ++k) {
       before += k < w ? s_w[k] : 0u;
       all += s_w[k];
     }
-    if (i < nblocks) partial[i] = before + inc - v;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (i0 + k < nblocks) partial[i0 + k] = before;
+      before += v[k];
+    }
     __syncthreads();
     if (threadIdx.x == 0) s_carry += all;
     __syncthreads();
@@ -245,9 +271,17 @@ sssp_scan_kernel(uint32_t* __restrict__ partial, uint32_t nblocks, State* st, ui
   if (threadIdx.x == 0) {
     st->edges = s_carry;
     st->relaxed += s_carry;
+    const Near nr = near_bucket(offsets, nb);
     uint32_t base = st->base;
-    if (st->jump && st->far_min != kInf) base = st->far_min;
+    if (nr.jump) {
+      if (st->far_min[par] != kInf) base = st->far_min[par];
+    } else {
+      const uint64_t b = (uint64_t)base + (uint64_t)nr.j * delta;
+      base = b > kDistMax ? kDistMax : (uint32_t)b;
+    }
     st->base = base;
+    st->count[par ^ 1u] = 0u;  // the next round appends there
+    st->far_min[par ^ 1u] = kInf;
     s_base = base;
   }
   __syncthreads();
@@ -255,12 +289,14 @@ sssp_scan_kernel(uint32_t* __restrict__ partial, uint32_t nblocks, State* st, ui
 }
 
 // Scanned degrees: deg[i] becomes the index of entry i's first edge among
-// the round's edges (near entries only; a thread scans 8 consecutive).
+// the round's edges (near entries only; a thread scans kPer consecutive).
 __global__ void __launch_bounds__(kThreads)
-sssp_edge_offsets_kernel(uint32_t n, const State* st, uint32_t* __restrict__ deg,
-                         const uint32_t* __restrict__ partial) {
+sssp_edge_offsets_kernel(uint32_t n, uint32_t* __restrict__ deg,
+                         const uint32_t* __restrict__ partial,
+                         const uint32_t* __restrict__ offsets, uint32_t nb) {
   __shared__ uint32_t s_w[kThreads / kWave];
-  const uint32_t near_lo = st->near_lo, near_hi = st->near_hi;
+  const Near nr = near_bucket(offsets, nb);
+  const uint32_t near_lo = nr.lo, near_hi = nr.hi;
   const uint32_t i0 = blockIdx.x * kBlockItems + threadIdx.x * kPer;
   uint32_t g[kPer], sum = 0;
 #pragma unroll
@@ -283,47 +319,107 @@ sssp_edge_offsets_kernel(uint32_t n, const State* st, uint32_t* __restrict__ deg
   }
 }
 
+// Last near entry whose first-edge index is <= e, searched in global memory
+// over [lo, hi) (eoff[lo] <= e).
+__device__ __forceinline__ uint32_t entry_of(const uint32_t* eoff, uint32_t lo, uint32_t hi,
+                                             uint32_t e) {
+  uint32_t len = hi - lo;
+  while (len > 0) {  // first entry whose first-edge index exceeds e
+    const uint32_t half = len >> 1;
+    if (eoff[lo + half] <= e) {
+      lo += half + 1;
+      len -= half + 1;
+    } else {
+      len = half;
+    }
+  }
+  return lo - 1;
+}
+
 // Edge-parallel relaxation of the near bucket.  Edge e of the round belongs
 // to the last near entry whose first-edge index is <= e (entries with no
-// edges share their successor's index and are passed over).
+// edges share their successor's index and are passed over).  A workgroup
+// takes 2048 consecutive edges at a time: two global searches bound the
+// entries they belong to, whose first-edge indices are staged in LDS (when
+// they fit) for the per-edge searches.  A relaxation first compares with a
+// plain load of the distance, which can only be larger than the current
+// value (distances only decrease), so skipping the atomic when it is not
+// larger loses nothing.  Improvements are appended with one atomic per
+// workgroup and chunk.
 __global__ void __launch_bounds__(kThreads)
 sssp_relax_kernel(const uint32_t* __restrict__ ok, const uint32_t* __restrict__ ov,
                   const uint64_t* __restrict__ row, const uint32_t* __restrict__ col,
                   const uint32_t* __restrict__ wt, uint32_t nv, uint32_t* dist, State* st,
-                  const uint32_t* __restrict__ eoff, uint32_t* pk, uint32_t* pv, uint32_t cap) {
+                  const uint32_t* __restrict__ eoff, uint32_t* pk, uint32_t* pv, uint32_t cap,
+                  const uint32_t* __restrict__ offsets, uint32_t nb, uint32_t par) {
+  __shared__ uint32_t s_eoff[kChunk];
+  __shared__ uint32_t s_rng[2];
+  __shared__ uint32_t s_w[kThreads / kWave];
+  __shared__ uint32_t s_base;
   const uint64_t edges = st->edges;
-  const uint32_t near_lo = st->near_lo, near_hi = st->near_hi;
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  // Every lane runs the same number of trips so the appends stay wave wide.
-  const uint64_t wave_first = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x - lane_id();
-  for (uint64_t eb = wave_first; eb < edges; eb += stride) {
-    const uint64_t e64 = eb + lane_id();
-    const uint32_t e = (uint32_t)e64;  // < edges <= 2^32 - 1 when used
-    bool put = false;
-    uint32_t nd = 0, u = 0;
-    if (e64 < edges) {
-      uint32_t lo = near_lo, len = near_hi - near_lo;
-      while (len > 0) {  // first entry whose first-edge index exceeds e
-        const uint32_t half = len >> 1;
-        if (eoff[lo + half] <= e) {
-          lo += half + 1;
-          len -= half + 1;
+  const Near nr = near_bucket(offsets, nb);
+  const uint32_t near_lo = nr.lo, near_hi = nr.hi;
+  for (uint64_t c0 = (uint64_t)blockIdx.x * kChunk; c0 < edges;
+       c0 += (uint64_t)gridDim.x * kChunk) {
+    const uint64_t c1 = c0 + kChunk < edges ? c0 + kChunk : edges;
+    if (threadIdx.x == 0) {
+      s_rng[0] = entry_of(eoff, near_lo, near_hi, (uint32_t)c0);
+      s_rng[1] = entry_of(eoff, near_lo, near_hi, (uint32_t)(c1 - 1));
+    }
+    __syncthreads();
+    const uint32_t i0 = s_rng[0], i1 = s_rng[1];
+    const uint32_t cnt = i1 - i0 + 1;
+    const bool staged = cnt <= kChunk;
+    if (staged)
+      for (uint32_t k = threadIdx.x; k < cnt; k += kThreads) s_eoff[k] = eoff[i0 + k];
+    __syncthreads();
+    uint32_t nd[kEdgePer], u[kEdgePer], nput = 0;
+    bool put[kEdgePer];
+#pragma unroll
+    for (int k = 0; k < kEdgePer; ++k) {
+      const uint64_t e64 = c0 + threadIdx.x + (uint64_t)k * kThreads;
+      put[k] = false;
+      nd[k] = 0;
+      u[k] = 0;
+      if (e64 < c1) {
+        const uint32_t e = (uint32_t)e64;
+        uint32_t item, first;
+        if (staged) {
+          uint32_t lo = 0, len = cnt;  // s_eoff[0] <= e
+          while (len > 0) {
+            const uint32_t half = len >> 1;
+            if (s_eoff[lo + half] <= e) {
+              lo += half + 1;
+              len -= half + 1;
+            } else {
+              len = half;
+            }
+          }
+          item = i0 + lo - 1;
+          first = s_eoff[lo - 1];
         } else {
-          len = half;
+          item = entry_of(eoff, i0, i1 + 1, e);
+          first = eoff[item];
+        }
+        const uint32_t v = ov[item];
+        const uint64_t ge = row[v] + (e - first);
+        const uint32_t t = col[ge];
+        if (t < nv) {
+          const uint32_t cand = sat_add(ok[item], wt[ge]);
+          if (cand < dist[t]) put[k] = atomicMin(&dist[t], cand) > cand;
+          nd[k] = cand;
+          u[k] = t;
+        } else {
+          st->bad_edge = 1u;
         }
       }
-      const uint32_t item = lo - 1;  // eoff[near_lo] == 0 <= e, so lo > near_lo
-      const uint32_t v = ov[item];
-      const uint64_t ge = row[v] + (e - eoff[item]);
-      u = col[ge];
-      if (u < nv) {
-        nd = sat_add(ok[item], wt[ge]);
-        put = atomicMin(&dist[u], nd) > nd;
-      } else {
-        st->bad_edge = 1u;
-      }
+      nput += put[k] ? 1u : 0u;
     }
-    wave_append(put, nd, u, st, pk, pv, cap, true);
+    uint32_t slot = group_reserve(nput, &st->count[par], &st->pushes, s_w, &s_base);
+#pragma unroll
+    for (int k = 0; k < kEdgePer; ++k)
+      if (put[k]) put_entry(slot++, nd[k], u[k], st, pk, pv, cap);
+    // group_reserve ends with a barrier: s_rng and s_eoff are free again
   }
 }
 
@@ -397,26 +493,26 @@ ms_status ms_sssp(const uint64_t* d_row, const uint32_t* d_col, const uint32_t* 
     ms_status rc = ms_pairs(pk, pv, ok, ov, offsets, n, nb, &fn, ms_ws, ms_ws_bytes, nullptr, s);
     if (rc != MS_OK) return rc;
     const uint32_t nblocks = (uint32_t)(((uint64_t)n + kBlockItems - 1) / kBlockItems);
-    hipLaunchKernelGGL(sssp_choose_kernel, dim3(1), dim3(kWave), 0, s, offsets, n, nb, delta, st);
+    const uint32_t par = (uint32_t)(acc.rounds & 1u);
     hipLaunchKernelGGL(sssp_filter_kernel, dim3(nblocks), dim3(kThreads), 0, s, ok, ov, n, d_row,
-                       d_dist, st, pk, pv, cap, deg, partial);
+                       d_dist, st, pk, pv, cap, deg, partial, offsets, nb, par);
     hipLaunchKernelGGL(sssp_scan_kernel, dim3(1), dim3(kThreads), 0, s, partial, nblocks, st, spl,
-                       nb, delta);
-    hipLaunchKernelGGL(sssp_edge_offsets_kernel, dim3(nblocks), dim3(kThreads), 0, s, n, st, deg,
-                       partial);
+                       nb, delta, offsets, par);
+    hipLaunchKernelGGL(sssp_edge_offsets_kernel, dim3(nblocks), dim3(kThreads), 0, s, n, deg,
+                       partial, offsets, nb);
     hipLaunchKernelGGL(sssp_relax_kernel, dim3(kExpandBlocks), dim3(kThreads), 0, s, ok, ov,
-                       d_row, d_col, d_wt, nv, d_dist, st, deg, pk, pv, cap);
+                       d_row, d_col, d_wt, nv, d_dist, st, deg, pk, pv, cap, offsets, nb, par);
     if (hipGetLastError() != hipSuccess) return MS_ERR_HIP;
-    uint32_t h[3];
+    uint32_t h[4];  // count[0], count[1], overflow, bad_edge
     if (hipMemcpyAsync(h, st, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
       return MS_ERR_HIP;
-    if (h[1]) return MS_ERR_WORKSPACE;  // cannot happen: the list holds nv + ne
-    if (h[2]) return MS_ERR_INVALID_ARG;  // an edge names a vertex >= nv
+    if (h[2]) return MS_ERR_WORKSPACE;  // cannot happen: the list holds nv + ne
+    if (h[3]) return MS_ERR_INVALID_ARG;  // an edge names a vertex >= nv
     acc.rounds += 1;
     acc.items_split += n;
     if (n > acc.max_pending) acc.max_pending = n;
-    n = h[0];
+    n = h[par];
   }
   State hs;
   if (hipMemcpyAsync(&hs, st, sizeof(hs), hipMemcpyDeviceToHost, s) != hipSuccess ||
