@@ -147,8 +147,8 @@ def workload(name):
     if name == "copy_2e28":
         return "copy", 1 << 28, 1, 0, 7
     if name.startswith("sssp_rmat_2e20"):
-        # sssp_rmat_2e20 (delta 100) or sssp_rmat_2e20_d<delta>
-        delta = int(name.split("_d")[1]) if "_d" in name else 100
+        # sssp_rmat_2e20 (delta 800, the fastest measured) or sssp_rmat_2e20_d<delta>
+        delta = int(name.split("_d")[1]) if "_d" in name else 800
         return "sssp", 20, 4_800_000, delta, 106
     if name == "batched_4096_m64":
         return "batched", 4096, 64, 8, 104
