@@ -244,13 +244,16 @@ __device__ __forceinline__ void tile_rank_reorder_write(const BF& bf, uint32_t (
     bk[j] = valid ? bf(k[j]) : 0u;
   }
   wave_order();
-  // ranking: Algorithm 3 per window + per-wavefront running counts
+  // ranking: Algorithm 3 per window + per-wavefront running counts.  The
+  // next window's count is read right after this window's store (a
+  // wavefront's LDS operations complete in order), so the read's latency
+  // overlaps the next window's ballots instead of stalling after them.
+  uint32_t before = lds_get(c.my_cnt + bk[0]);
 #pragma unroll
   for (int j = 0; j < NW; ++j) {
     const bool valid = FULL || wbase + (uint32_t)(j * kWave) + lane < tcount;
     const uint64_t mm = match_bucket<BITS>(bk[j], FULL ? ~0ull : ballot(valid));
     const uint32_t r = count_below(mm), cnt = popc64(mm);
-    const uint32_t before = lds_get(c.my_cnt + bk[j]);
     lr[j] = before + r;
     // With values (more registers live), materialise the rank now: otherwise
     // the compiler sinks it past the barriers and keeps both halves of every
@@ -263,6 +266,7 @@ __device__ __forceinline__ void tile_rank_reorder_write(const BF& bf, uint32_t (
     // it stores that same value too.
     lds_put(c.my_cnt + bk[j], before + cnt);
     wave_order();
+    if (j + 1 < NW) before = lds_get(c.my_cnt + bk[j + 1]);
   }
   group_sync<WPG>();
   // exclusive scan of the bucket-major table: entry e = b*WPG + wave
