@@ -230,7 +230,17 @@ struct TileCtx {
 
 constexpr int kCntStride = kMaxBuckets + 1;
 
-template <int BITS, bool KV, int WPG, int NW, bool FULL, class BF, class AfterStage>
+// The post-scan visits a chunk's tiles last to first.  The pre-scan swept
+// every chunk first to last, so the last lines it read -- the ends of the
+// chunks -- are the ones still in the memory-side cache when the post-scan
+// starts; beginning there re-reads them from the cache instead of HBM.
+// Each tile then takes its bucket runs from the top of what is left of the
+// chunk's bucket ranges, which places every element exactly where the
+// forward order would (the tile's local order is unchanged).
+constexpr bool kReverseTiles = true;
+
+template <int BITS, bool KV, int WPG, int NW, bool FULL, class BF, class AfterStage,
+          bool REV = false>
 __device__ __forceinline__ void tile_rank_reorder_write(const BF& bf, uint32_t (&k)[NW],
                                                         uint32_t (&v)[NW], const TileCtx<KV>& c,
                                                         AfterStage after_stage) {
@@ -296,8 +306,13 @@ __device__ __forceinline__ void tile_rank_reorder_write(const BF& bf, uint32_t (
   for (uint32_t b = tid_g; b < m; b += WPG * kWave) {
     const uint32_t st = c.grp_cnt[b];
     const uint32_t nx = (b + 1 < m) ? c.grp_cnt[b + 1] : tcount;
-    c.delta[b] = c.run[b] - st;
-    c.run[b] += nx - st;
+    if (REV) {  // tiles visited last to first: run[b] is the end of what is left
+      c.run[b] -= nx - st;
+      c.delta[b] = c.run[b] - st;
+    } else {
+      c.delta[b] = c.run[b] - st;
+      c.run[b] += nx - st;
+    }
   }
   // local reorder: slot = tile base of (bucket, wavefront) + rank
 #pragma unroll
@@ -390,10 +405,20 @@ postscan_kernel(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) offsets[m] = plan.n;
     __syncthreads();
+    // Running output position of each bucket in the group's chunk: its
+    // start, or with tiles visited last to first its end (the next chunk's
+    // start, or the bucket's end for the last chunk).
     for (uint32_t i = threadIdx.x; i < GPB * m; i += WPB * kWave) {
       uint32_t gg = i / m, b = i % m;
       uint32_t cc = blockIdx.x * GPB + gg;
-      s_run[gg * kMaxBuckets + b] = (cc < plan.L0) ? s_cnt[b] + G[b * plan.L0 + cc] : 0u;
+      uint32_t r = 0;
+      if (cc < plan.L0) {
+        if (!kReverseTiles || MODE == kDirect)
+          r = s_cnt[b] + G[b * plan.L0 + cc];
+        else
+          r = s_cnt[b] + (cc + 1 < plan.L0 ? G[b * plan.L0 + cc + 1] : totals[b]);
+      }
+      s_run[gg * kMaxBuckets + b] = r;
     }
     __syncthreads();
   }
@@ -483,12 +508,20 @@ postscan_kernel(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict
       const uint32_t tcount = FULL ? (uint32_t)T : min((uint32_t)T, len - ti * T);
       TileCtx<KV> ctx{s_k, s_v, s_b, my_cnt, grp_cnt, run, delta, s_tmp + g * WPG,
                       keys_out, vals_out, m, tcount, wg, lane, tid_g};
-      tile_rank_reorder_write<BITS, KV, WPG, NW, FULL>(
-          bf, k, v, ctx, [&] { if (ti + 1 < ntiles) load_tile(ti + 1); });
+      auto next = [&] {
+        if (kReverseTiles) {
+          if (ti > 0) load_tile(ti - 1);
+        } else if (ti + 1 < ntiles) {
+          load_tile(ti + 1);
+        }
+      };
+      tile_rank_reorder_write<BITS, KV, WPG, NW, FULL, decltype(bf), decltype(next),
+                              kReverseTiles>(bf, k, v, ctx, next);
     };
 
-    if (ntiles > 0) load_tile(0);
-    for (uint32_t ti = 0; ti < ntiles; ++ti) {
+    if (ntiles > 0) load_tile(kReverseTiles ? ntiles - 1 : 0);
+    for (uint32_t it = 0; it < ntiles; ++it) {
+      const uint32_t ti = kReverseTiles ? ntiles - 1 - it : it;
       if (len - ti * T >= (uint32_t)T)
         tile(ti, std::true_type{});
       else
