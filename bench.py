@@ -140,8 +140,11 @@ def workload(name):
         parts = name.split("_")
         bits = int(parts[3][1:])
         return parts[1] + "_ident", 1 << int(parts[2][2:]), 1 << bits, 0, 120 + bits
-    if name in ("radix_pairs_2e28", "radix_keys_2e28"):
-        return name.rsplit("_", 1)[0], 1 << 28, 256, 0, 105
+    if name.startswith("radix_pairs_2e28") or name.startswith("radix_keys_2e28"):
+        # radix_pairs_2e28 (8-bit digits) or radix_pairs_2e28_b<bits>; the
+        # shift slot carries the digit width
+        bits = int(name.split("_b")[1]) if "_b" in name else 8
+        return name.split("_2e28")[0], 1 << 28, 1 << bits, bits, 105
     if name == "range_2e27_m256":
         return "range", 1 << 27, 256, 0, 103
     if name == "copy_2e28":
@@ -662,7 +665,7 @@ def main():
     radix = kind.startswith("radix")
     op = (ms.OP_RADIX_SORT_PAIRS if kv else ms.OP_RADIX_SORT) if radix else \
         (ms.OP_PAIRS if kv else ms.OP_KEYS)
-    ws = torch.empty(max(256, ms.workspace_size(op, n, 256 if radix else m, 0, opt)), dtype=torch.uint8,
+    ws = torch.empty(max(256, ms.workspace_size(op, n, m, 0, opt)), dtype=torch.uint8,
                      device=dev)
     # powers of two: shift/mask; other m: delta buckets floor(k / ceil(2^32 / m))
     pow2 = m & (m - 1) == 0
@@ -670,7 +673,7 @@ def main():
 
     def step(o):
         if radix:
-            ms.radix_sort(dk, dv, 8, keys_out=ok, vals_out=ov, options=o, ws=ws)
+            ms.radix_sort(dk, dv, shift, keys_out=ok, vals_out=ov, options=o, ws=ws)
         elif kv:
             ms.pairs(dk, dv, m, fn, keys_out=ok, vals_out=ov, offsets=off, options=o, ws=ws)
         else:
@@ -763,7 +766,7 @@ def main():
         "eager_value": round(units / (ms_per_step * 1e-3) / 1e9, 3),
         "graph_value": round(units / (graph_ms * 1e-3) / 1e9, 3),
         "config": {"workload": args.workload, "n": n, "m": m,
-                   "bucket": ("radix 4 x 8-bit digits" if radix else
+                   "bucket": ("radix %d x %d-bit digits" % (-(-32 // shift), shift) if radix else
                               "identity (keys < m)" if ident else
                               "shift_mask" if pow2 else "delta ceil(2^32/m)"),
                    "shift": shift, "kv": kv, "seed": seed,
@@ -788,7 +791,7 @@ def main():
         line["roofline"]["frac_of_copy_ceiling"] = round(achieved / ceiling, 4)
     if radix:
         line["roofline"]["whole_call_algorithmic_GBps"] = round(
-            n * 4 * (20 if kv else 12) / (timed_ms * 1e-3) / 1e9, 1)
+            n * -(-32 // shift) * (20 if kv else 12) / (timed_ms * 1e-3) / 1e9, 1)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(kind, keys, vals, m, shift, args.cpu_seconds)
     print(json.dumps(line), flush=True)
