@@ -623,8 +623,8 @@ def bench_range(args, n, m, seed, dev):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only (multisplit runs on a single "
-              "MI355X here); --gpus %d is not supported" % args.gpus, file=sys.stderr)
+        print("bench.py: the multisplit library runs on one GPU; only --gpus 1 is "
+              "measured (--gpus %d is not supported)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

@@ -50,7 +50,7 @@ typedef enum {
   MS_ERR_HIP = -3,         /* a HIP runtime call or kernel launch failed     */
   MS_ERR_BUCKET_RANGE = -4,/* bucket function can produce ids >= m           */
   MS_ERR_TIMEOUT = -5,     /* a bounded device wait expired                  */
-  MS_ERR_UNSUPPORTED = -6  /* valid request this build does not implement    */
+  MS_ERR_UNSUPPORTED = -6  /* valid request the library does not implement   */
 } ms_status;
 
 /* Human-readable name of a status code (static string). */
