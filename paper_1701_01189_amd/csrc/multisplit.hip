@@ -120,6 +120,10 @@ Plan make_plan(size_t n, uint32_t m, const Shape& s, bool kv) {
   if (L0 == 0) L0 = 1;
   uint64_t tpc = (tiles + L0 - 1) / L0;
   if (tpc == 0) tpc = 1;
+  // A chunk's length is a 32-bit count: near n = 2^32 a forced small chunk
+  // count gets one more chunk rather than a length that wraps.
+  const uint64_t max_tpc = 0xFFFFFFFFull / p.tile;
+  if (tpc > max_tpc) tpc = max_tpc;
   L0 = (tiles + tpc - 1) / tpc;
   if (L0 == 0) L0 = 1;
   p.L0 = (uint32_t)L0;

@@ -169,3 +169,13 @@ def test_sssp_host_checks(L):
     assert call(c=None) == invalid and call(w=None) == invalid
     assert call(nv=1 << 31, ne=1 << 31) == invalid
     assert call(wsb=need - 1) == workspace
+
+
+def test_plan_near_2e32_keeps_chunk_lengths_in_range(L):
+    from paper_1701_01189_amd.binding import OptionsC
+    n = (1 << 32) - 2  # the largest accepted size
+    one = OptionsC()
+    one.max_chunks = 1  # asks for a single chunk, whose length would not fit 32 bits
+    assert L.ms_workspace_size(1, n, 32, 0, ctypes.byref(one)) > 0
+    assert L.ms_workspace_size(1, n, 32, 0, None) > 0
+    assert L.ms_workspace_size(1, n + 1, 32, 0, None) == 0

@@ -1,5 +1,5 @@
 """GPU multisplit past 2^31 elements, where any index held in a signed 32-bit
-integer would overflow (the library takes n < 2^32 - 1).
+integer would overflow, up to the largest size the library takes (2^32 - 2).
 
 At this size the oracle is too slow to run element by element, so the output
 is checked against the properties that determine the unique stable
@@ -100,3 +100,20 @@ def test_keys_past_2e31_delta_256():
     sin = sum(int(u32(kin[s:s + SLICE]).sum()) for s in range(0, n, SLICE))
     sout = sum(int(u32(ko[s:s + SLICE]).sum()) for s in range(0, n, SLICE))
     assert sin == sout
+
+
+def test_pairs_at_the_largest_size():
+    from paper_1701_01189_amd import binding as ms
+    n = (1 << 32) - 2  # the largest n the library accepts
+    say("case large pairs n=%d m=8 shift" % n)
+    g = torch.Generator(device="cuda").manual_seed(2033)
+    kin = torch.randint(-(1 << 31), 1 << 31, (n,), dtype=torch.int32, device="cuda",
+                        generator=g)
+    vin = torch.empty(n, dtype=torch.int32, device="cuda")
+    for s in range(0, n, SLICE):
+        e = min(n, s + SLICE)
+        vin[s:e] = torch.arange(s, e, dtype=torch.int64, device="cuda").to(torch.int32)
+    ko, vo, off = ms.pairs(kin, vin, 8, ms.BucketFn.shift_mask(29, 7))
+    torch.cuda.synchronize()
+    del vin
+    check_stable_multisplit(kin, ko, vo, off, n, 8, "shift", 29)
