@@ -21,9 +21,9 @@
 // Delta, B or the order of the atomic updates.
 //
 // Work balance: relaxation is edge parallel.  The near vertices' degrees are
-// scanned (a reduce-then-scan over 2048-entry blocks) and each edge finds
-// its vertex by binary search in the scanned degrees, so high-degree and
-// low-degree vertices cost the same per edge.
+// scanned (inside each 1024-entry filter workgroup, then over the workgroup
+// sums) and each edge finds its vertex by binary search in the scanned
+// degrees, so high-degree and low-degree vertices cost the same per edge.
 //
 // One host synchronisation per round reads the pending count, which sizes
 // the next multisplit.  Everything else (the near bucket, the base, the
@@ -179,6 +179,7 @@ sssp_filter_kernel(const uint32_t* __restrict__ ok, const uint32_t* __restrict__
                    uint32_t nb, uint32_t par) {
   __shared__ uint32_t s_w[kThreads / kWave];
   __shared__ uint32_t s_base;
+  __shared__ uint32_t s_deg[kBlockItems];
   const Near nr = near_bucket(offsets, nb);
   const uint32_t near_lo = nr.lo, near_hi = nr.hi, far_lo = nr.hi;
   const bool jump = nr.jump;
@@ -193,7 +194,7 @@ sssp_filter_kernel(const uint32_t* __restrict__ ok, const uint32_t* __restrict__
   uint32_t dv[kPer];
 #pragma unroll
   for (int e = 0; e < kPer; ++e) dv[e] = dist[v[e]];  // v < nv on every lane
-  uint32_t sum = 0, fmin = kInf, nkeep = 0;
+  uint32_t fmin = kInf, nkeep = 0;
   bool keep[kPer];
 #pragma unroll
   for (int e = 0; e < kPer; ++e) {
@@ -202,11 +203,9 @@ sssp_filter_kernel(const uint32_t* __restrict__ ok, const uint32_t* __restrict__
     keep[e] = valid && i >= far_lo;
     nkeep += keep[e] ? 1u : 0u;
     if (keep[e] && d[e] < fmin) fmin = d[e];
-    if (i < n && i >= near_lo && i < near_hi) {
-      const uint32_t g = valid ? (uint32_t)(row[v[e] + 1] - row[v[e]]) : 0u;
-      deg[i] = g;
-      sum += g;
-    }
+    uint32_t g = 0;
+    if (valid && i >= near_lo && i < near_hi) g = (uint32_t)(row[v[e] + 1] - row[v[e]]);
+    s_deg[(uint32_t)e * kThreads + threadIdx.x] = g;
   }
   uint32_t slot = group_reserve(nkeep, &st->count[par], nullptr, s_w, &s_base);
 #pragma unroll
@@ -219,15 +218,33 @@ sssp_filter_kernel(const uint32_t* __restrict__ ok, const uint32_t* __restrict__
     }
     if (lane_id() == 0 && fmin != kInf) atomicMin(&st->far_min[par], fmin);
   }
-  // workgroup sum of near degrees
-  const uint32_t inc = ms::wave_inclusive_scan(sum, lane_id());
-  if (lane_id() == kWave - 1) s_w[threadIdx.x / kWave] = inc;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t t = 0;
-    for (int k = 0; k < kThreads / kWave; ++k) t += s_w[k];
-    partial[blockIdx.x] = t;
+  // Exclusive prefix of the near degrees inside the workgroup, in entry
+  // order (a thread scans kPer consecutive entries), and the workgroup total.
+  // An entry's first edge in the round is partial[workgroup] (scanned by the
+  // scan kernel) plus this local prefix.  group_reserve's last barrier made
+  // s_deg complete.
+  uint32_t gl[kPer], tsum = 0;
+#pragma unroll
+  for (int e = 0; e < kPer; ++e) {
+    gl[e] = s_deg[threadIdx.x * kPer + e];
+    tsum += gl[e];
   }
+  const uint32_t lane = lane_id(), w = threadIdx.x / kWave;
+  const uint32_t inc = ms::wave_inclusive_scan(tsum, lane);
+  if (lane == kWave - 1) s_w[w] = inc;
+  __syncthreads();
+  uint32_t run = inc - tsum, total = 0;
+  for (uint32_t k = 0; k < kThreads / kWave; ++k) {
+    run += k < w ? s_w[k] : 0u;
+    total += s_w[k];
+  }
+#pragma unroll
+  for (int e = 0; e < kPer; ++e) {
+    const uint32_t i = b0 + threadIdx.x * kPer + (uint32_t)e;
+    if (i < n) deg[i] = run;
+    run += gl[e];
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = total;
 }
 
 // Exclusive scan of the per-block degree sums (one workgroup); the total is
@@ -288,45 +305,21 @@ sssp_scan_kernel(uint32_t* __restrict__ partial, uint32_t nblocks, State* st, ui
   write_splitters(spl, nb, s_base, delta);
 }
 
-// Scanned degrees: deg[i] becomes the index of entry i's first edge among
-// the round's edges (near entries only; a thread scans kPer consecutive).
-__global__ void __launch_bounds__(kThreads)
-sssp_edge_offsets_kernel(uint32_t n, uint32_t* __restrict__ deg,
-                         const uint32_t* __restrict__ partial,
-                         const uint32_t* __restrict__ offsets, uint32_t nb) {
-  __shared__ uint32_t s_w[kThreads / kWave];
-  const Near nr = near_bucket(offsets, nb);
-  const uint32_t near_lo = nr.lo, near_hi = nr.hi;
-  const uint32_t i0 = blockIdx.x * kBlockItems + threadIdx.x * kPer;
-  uint32_t g[kPer], sum = 0;
-#pragma unroll
-  for (int e = 0; e < kPer; ++e) {
-    const uint32_t i = i0 + (uint32_t)e;
-    g[e] = (i < n && i >= near_lo && i < near_hi) ? deg[i] : 0u;
-    sum += g[e];
-  }
-  const uint32_t lane = lane_id(), w = threadIdx.x / kWave;
-  const uint32_t inc = ms::wave_inclusive_scan(sum, lane);
-  if (lane == kWave - 1) s_w[w] = inc;
-  __syncthreads();
-  uint32_t run = partial[blockIdx.x] + inc - sum;
-  for (uint32_t k = 0; k < w; ++k) run += s_w[k];
-#pragma unroll
-  for (int e = 0; e < kPer; ++e) {
-    const uint32_t i = i0 + (uint32_t)e;
-    if (i < n && i >= near_lo && i < near_hi) deg[i] = run;
-    run += g[e];
-  }
+// First-edge index of entry i in this round: its workgroup's scanned degree
+// sum plus its prefix inside the workgroup.
+__device__ __forceinline__ uint32_t first_edge(const uint32_t* loc, const uint32_t* partial,
+                                               uint32_t i) {
+  return partial[i / kBlockItems] + loc[i];
 }
 
 // Last near entry whose first-edge index is <= e, searched in global memory
-// over [lo, hi) (eoff[lo] <= e).
-__device__ __forceinline__ uint32_t entry_of(const uint32_t* eoff, uint32_t lo, uint32_t hi,
-                                             uint32_t e) {
+// over [lo, hi) (entry lo's first edge is <= e).
+__device__ __forceinline__ uint32_t entry_of(const uint32_t* loc, const uint32_t* partial,
+                                             uint32_t lo, uint32_t hi, uint32_t e) {
   uint32_t len = hi - lo;
   while (len > 0) {  // first entry whose first-edge index exceeds e
     const uint32_t half = len >> 1;
-    if (eoff[lo + half] <= e) {
+    if (first_edge(loc, partial, lo + half) <= e) {
       lo += half + 1;
       len -= half + 1;
     } else {
@@ -350,7 +343,8 @@ __global__ void __launch_bounds__(kThreads)
 sssp_relax_kernel(const uint32_t* __restrict__ ok, const uint32_t* __restrict__ ov,
                   const uint64_t* __restrict__ row, const uint32_t* __restrict__ col,
                   const uint32_t* __restrict__ wt, uint32_t nv, uint32_t* dist, State* st,
-                  const uint32_t* __restrict__ eoff, uint32_t* pk, uint32_t* pv, uint32_t cap,
+                  const uint32_t* __restrict__ loc, const uint32_t* __restrict__ partial,
+                  uint32_t* pk, uint32_t* pv, uint32_t cap,
                   const uint32_t* __restrict__ offsets, uint32_t nb, uint32_t par) {
   __shared__ uint32_t s_eoff[kChunk];
   __shared__ uint32_t s_rng[2];
@@ -363,15 +357,16 @@ sssp_relax_kernel(const uint32_t* __restrict__ ok, const uint32_t* __restrict__ 
        c0 += (uint64_t)gridDim.x * kChunk) {
     const uint64_t c1 = c0 + kChunk < edges ? c0 + kChunk : edges;
     if (threadIdx.x == 0) {
-      s_rng[0] = entry_of(eoff, near_lo, near_hi, (uint32_t)c0);
-      s_rng[1] = entry_of(eoff, near_lo, near_hi, (uint32_t)(c1 - 1));
+      s_rng[0] = entry_of(loc, partial, near_lo, near_hi, (uint32_t)c0);
+      s_rng[1] = entry_of(loc, partial, near_lo, near_hi, (uint32_t)(c1 - 1));
     }
     __syncthreads();
     const uint32_t i0 = s_rng[0], i1 = s_rng[1];
     const uint32_t cnt = i1 - i0 + 1;
     const bool staged = cnt <= kChunk;
     if (staged)
-      for (uint32_t k = threadIdx.x; k < cnt; k += kThreads) s_eoff[k] = eoff[i0 + k];
+      for (uint32_t k = threadIdx.x; k < cnt; k += kThreads)
+        s_eoff[k] = first_edge(loc, partial, i0 + k);
     __syncthreads();
     uint32_t nd[kEdgePer], u[kEdgePer], nput = 0;
     bool put[kEdgePer];
@@ -398,8 +393,8 @@ sssp_relax_kernel(const uint32_t* __restrict__ ok, const uint32_t* __restrict__ 
           item = i0 + lo - 1;
           first = s_eoff[lo - 1];
         } else {
-          item = entry_of(eoff, i0, i1 + 1, e);
-          first = eoff[item];
+          item = entry_of(loc, partial, i0, i1 + 1, e);
+          first = first_edge(loc, partial, item);
         }
         const uint32_t v = ov[item];
         const uint64_t ge = row[v] + (e - first);
@@ -498,10 +493,9 @@ ms_status ms_sssp(const uint64_t* d_row, const uint32_t* d_col, const uint32_t* 
                        d_dist, st, pk, pv, cap, deg, partial, offsets, nb, par);
     hipLaunchKernelGGL(sssp_scan_kernel, dim3(1), dim3(kThreads), 0, s, partial, nblocks, st, spl,
                        nb, delta, offsets, par);
-    hipLaunchKernelGGL(sssp_edge_offsets_kernel, dim3(nblocks), dim3(kThreads), 0, s, n, deg,
-                       partial, offsets, nb);
     hipLaunchKernelGGL(sssp_relax_kernel, dim3(kExpandBlocks), dim3(kThreads), 0, s, ok, ov,
-                       d_row, d_col, d_wt, nv, d_dist, st, deg, pk, pv, cap, offsets, nb, par);
+                       d_row, d_col, d_wt, nv, d_dist, st, deg, partial, pk, pv, cap, offsets, nb,
+                       par);
     if (hipGetLastError() != hipSuccess) return MS_ERR_HIP;
     uint32_t h[4];  // count[0], count[1], overflow, bad_edge
     if (hipMemcpyAsync(h, st, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||
