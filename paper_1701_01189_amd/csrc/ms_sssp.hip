@@ -51,6 +51,7 @@ constexpr uint32_t kBlockItems = kThreads * kPer;  // entries per filter workgro
 constexpr int kEdgePer = 8;
 constexpr uint32_t kChunk = kThreads * kEdgePer;   // edges per relaxation chunk
 constexpr uint32_t kExpandBlocks = 1024;           // 4 workgroups per CU
+constexpr uint32_t kFusedSums = 4096;  // workgroup sums the relaxation scans in LDS
 constexpr size_t kAlign = 256;
 
 // Loop state in device memory (one aligned slot of the workspace).  The
@@ -247,47 +248,55 @@ sssp_filter_kernel(const uint32_t* __restrict__ ok, const uint32_t* __restrict__
   if (threadIdx.x == 0) partial[blockIdx.x] = total;
 }
 
-// Exclusive scan of the per-block degree sums (one workgroup); the total is
-// this round's edge count.  Then moves the base (up to the near bucket's
-// lower edge, or to the least pending distance in a jump round) and writes
-// the next round's splitters.
-__global__ void __launch_bounds__(kThreads)
-sssp_scan_kernel(uint32_t* __restrict__ partial, uint32_t nblocks, State* st, uint32_t* spl,
-                 uint32_t nb, uint32_t delta, const uint32_t* __restrict__ offsets, uint32_t par) {
-  __shared__ uint32_t s_w[kThreads / kWave];
-  __shared__ uint32_t s_carry, s_base;
+// Exclusive scan of count per-workgroup degree sums from src into dst (dst
+// may be src, or an LDS array); returns the total, this round's edge count.
+// Four consecutive sums per thread per pass.  Every thread of the workgroup
+// calls it.
+__device__ __forceinline__ uint32_t group_scan_sums(const uint32_t* src, uint32_t count,
+                                                    uint32_t* dst, uint32_t* s_w,
+                                                    uint32_t* s_carry) {
   const uint32_t lane = lane_id(), w = threadIdx.x / kWave;
-  if (threadIdx.x == 0) s_carry = 0;
+  if (threadIdx.x == 0) *s_carry = 0;
   __syncthreads();
-  // 4 consecutive sums per thread per pass
-  for (uint32_t b = 0; b < nblocks; b += 4 * kThreads) {
+  for (uint32_t b = 0; b < count; b += 4 * kThreads) {
     const uint32_t i0 = b + 4 * threadIdx.x;
     uint32_t v[4], t = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      v[k] = i0 + k < nblocks ? partial[i0 + k] : 0u;
+      v[k] = i0 + k < count ? src[i0 + k] : 0u;
       t += v[k];
     }
     const uint32_t inc = ms::wave_inclusive_scan(t, lane);
     if (lane == kWave - 1) s_w[w] = inc;
     __syncthreads();
-    uint32_t before = s_carry + inc - t, all = 0;
+    uint32_t before = *s_carry + inc - t, all = 0;
     for (uint32_t k = 0; k < kThreads / kWave; ++k) {
       before += k < w ? s_w[k] : 0u;
       all += s_w[k];
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      if (i0 + k < nblocks) partial[i0 + k] = before;
+      if (i0 + k < count) dst[i0 + k] = before;
       before += v[k];
     }
     __syncthreads();
-    if (threadIdx.x == 0) s_carry += all;
+    if (threadIdx.x == 0) *s_carry += all;
     __syncthreads();
   }
+  return *s_carry;
+}
+
+// End of a round's bookkeeping (one workgroup): records the edge count,
+// moves the base (up to the near bucket's lower edge, or to the least
+// pending distance in a jump round), clears the next round's counters and
+// writes the next round's splitters.  Every thread of the workgroup calls it.
+__device__ __forceinline__ void finish_round(State* st, uint32_t edges,
+                                             const uint32_t* offsets, uint32_t nb,
+                                             uint32_t par, uint32_t* spl, uint32_t delta,
+                                             uint32_t* s_base) {
   if (threadIdx.x == 0) {
-    st->edges = s_carry;
-    st->relaxed += s_carry;
+    st->edges = edges;
+    st->relaxed += edges;
     const Near nr = near_bucket(offsets, nb);
     uint32_t base = st->base;
     if (nr.jump) {
@@ -299,10 +308,22 @@ sssp_scan_kernel(uint32_t* __restrict__ partial, uint32_t nblocks, State* st, ui
     st->base = base;
     st->count[par ^ 1u] = 0u;  // the next round appends there
     st->far_min[par ^ 1u] = kInf;
-    s_base = base;
+    *s_base = base;
   }
   __syncthreads();
-  write_splitters(spl, nb, s_base, delta);
+  write_splitters(spl, nb, *s_base, delta);
+}
+
+// The scan of the per-workgroup degree sums as a kernel of its own (one
+// workgroup), for rounds with more filter workgroups than the relaxation
+// kernel scans in LDS.
+__global__ void __launch_bounds__(kThreads)
+sssp_scan_kernel(uint32_t* __restrict__ partial, uint32_t nblocks, State* st, uint32_t* spl,
+                 uint32_t nb, uint32_t delta, const uint32_t* __restrict__ offsets, uint32_t par) {
+  __shared__ uint32_t s_w[kThreads / kWave];
+  __shared__ uint32_t s_carry, s_base;
+  const uint32_t total = group_scan_sums(partial, nblocks, partial, s_w, &s_carry);
+  finish_round(st, total, offsets, nb, par, spl, delta, &s_base);
 }
 
 // First-edge index of entry i in this round: its workgroup's scanned degree
@@ -339,26 +360,38 @@ __device__ __forceinline__ uint32_t entry_of(const uint32_t* loc, const uint32_t
 // value (distances only decrease), so skipping the atomic when it is not
 // larger loses nothing.  Improvements are appended with one atomic per
 // workgroup and chunk.
+template <bool FUSED>
 __global__ void __launch_bounds__(kThreads)
 sssp_relax_kernel(const uint32_t* __restrict__ ok, const uint32_t* __restrict__ ov,
                   const uint64_t* __restrict__ row, const uint32_t* __restrict__ col,
                   const uint32_t* __restrict__ wt, uint32_t nv, uint32_t* dist, State* st,
                   const uint32_t* __restrict__ loc, const uint32_t* __restrict__ partial,
-                  uint32_t* pk, uint32_t* pv, uint32_t cap,
-                  const uint32_t* __restrict__ offsets, uint32_t nb, uint32_t par) {
+                  uint32_t nblocks, uint32_t* pk, uint32_t* pv, uint32_t cap,
+                  const uint32_t* __restrict__ offsets, uint32_t nb, uint32_t par,
+                  uint32_t* spl, uint32_t delta) {
   __shared__ uint32_t s_eoff[kChunk];
+  __shared__ uint32_t s_part[FUSED ? kFusedSums : 1];
   __shared__ uint32_t s_rng[2];
   __shared__ uint32_t s_w[kThreads / kWave];
-  __shared__ uint32_t s_base;
-  const uint64_t edges = st->edges;
+  __shared__ uint32_t s_base, s_carry;
+  uint64_t edges;
+  if (FUSED) {
+    // Every workgroup scans the (few) per-workgroup degree sums into LDS;
+    // workgroup 0 also does the round's bookkeeping.
+    edges = group_scan_sums(partial, nblocks, s_part, s_w, &s_carry);
+    if (blockIdx.x == 0) finish_round(st, (uint32_t)edges, offsets, nb, par, spl, delta, &s_base);
+  } else {
+    edges = st->edges;
+  }
+  const uint32_t* part = FUSED ? s_part : partial;  // scanned sums
   const Near nr = near_bucket(offsets, nb);
   const uint32_t near_lo = nr.lo, near_hi = nr.hi;
   for (uint64_t c0 = (uint64_t)blockIdx.x * kChunk; c0 < edges;
        c0 += (uint64_t)gridDim.x * kChunk) {
     const uint64_t c1 = c0 + kChunk < edges ? c0 + kChunk : edges;
     if (threadIdx.x == 0) {
-      s_rng[0] = entry_of(loc, partial, near_lo, near_hi, (uint32_t)c0);
-      s_rng[1] = entry_of(loc, partial, near_lo, near_hi, (uint32_t)(c1 - 1));
+      s_rng[0] = entry_of(loc, part, near_lo, near_hi, (uint32_t)c0);
+      s_rng[1] = entry_of(loc, part, near_lo, near_hi, (uint32_t)(c1 - 1));
     }
     __syncthreads();
     const uint32_t i0 = s_rng[0], i1 = s_rng[1];
@@ -366,7 +399,7 @@ sssp_relax_kernel(const uint32_t* __restrict__ ok, const uint32_t* __restrict__ 
     const bool staged = cnt <= kChunk;
     if (staged)
       for (uint32_t k = threadIdx.x; k < cnt; k += kThreads)
-        s_eoff[k] = first_edge(loc, partial, i0 + k);
+        s_eoff[k] = first_edge(loc, part, i0 + k);
     __syncthreads();
     uint32_t nd[kEdgePer], u[kEdgePer], nput = 0;
     bool put[kEdgePer];
@@ -393,8 +426,8 @@ sssp_relax_kernel(const uint32_t* __restrict__ ok, const uint32_t* __restrict__ 
           item = i0 + lo - 1;
           first = s_eoff[lo - 1];
         } else {
-          item = entry_of(loc, partial, i0, i1 + 1, e);
-          first = first_edge(loc, partial, item);
+          item = entry_of(loc, part, i0, i1 + 1, e);
+          first = first_edge(loc, part, item);
         }
         const uint32_t v = ov[item];
         const uint64_t ge = row[v] + (e - first);
@@ -491,11 +524,17 @@ ms_status ms_sssp(const uint64_t* d_row, const uint32_t* d_col, const uint32_t* 
     const uint32_t par = (uint32_t)(acc.rounds & 1u);
     hipLaunchKernelGGL(sssp_filter_kernel, dim3(nblocks), dim3(kThreads), 0, s, ok, ov, n, d_row,
                        d_dist, st, pk, pv, cap, deg, partial, offsets, nb, par);
-    hipLaunchKernelGGL(sssp_scan_kernel, dim3(1), dim3(kThreads), 0, s, partial, nblocks, st, spl,
-                       nb, delta, offsets, par);
-    hipLaunchKernelGGL(sssp_relax_kernel, dim3(kExpandBlocks), dim3(kThreads), 0, s, ok, ov,
-                       d_row, d_col, d_wt, nv, d_dist, st, deg, partial, pk, pv, cap, offsets, nb,
-                       par);
+    if (nblocks <= kFusedSums) {
+      hipLaunchKernelGGL(sssp_relax_kernel<true>, dim3(kExpandBlocks), dim3(kThreads), 0, s, ok,
+                         ov, d_row, d_col, d_wt, nv, d_dist, st, deg, partial, nblocks, pk, pv,
+                         cap, offsets, nb, par, spl, delta);
+    } else {
+      hipLaunchKernelGGL(sssp_scan_kernel, dim3(1), dim3(kThreads), 0, s, partial, nblocks, st,
+                         spl, nb, delta, offsets, par);
+      hipLaunchKernelGGL(sssp_relax_kernel<false>, dim3(kExpandBlocks), dim3(kThreads), 0, s, ok,
+                         ov, d_row, d_col, d_wt, nv, d_dist, st, deg, partial, nblocks, pk, pv,
+                         cap, offsets, nb, par, spl, delta);
+    }
     if (hipGetLastError() != hipSuccess) return MS_ERR_HIP;
     uint32_t h[4];  // count[0], count[1], overflow, bad_edge
     if (hipMemcpyAsync(h, st, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||

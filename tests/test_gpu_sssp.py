@@ -112,6 +112,21 @@ def test_sssp_rmat_full_size_vs_oracle():
         say("  rounds=%d relaxed=%d pushes=%d" % (st["rounds"], st["edges_relaxed"], st["pushes"]))
 
 
+def test_sssp_rounds_past_the_fused_scan():
+    from paper_1701_01189_amd import binding as ms
+    # one huge bucket (delta 10^7): every round relaxes the whole frontier,
+    # which grows about fourfold a round until it peaks at 4.48 M improved
+    # vertices (a CPU count of this graph), so the pending list passes 4096
+    # filter workgroups (4 Mi entries) and the degree sums are scanned by
+    # their own kernel in those rounds
+    row, col, wt = random_graph(77, 1 << 23, 1 << 25, 1000)
+    say("case sssp large rounds nv=%d ne=%d" % (1 << 23, 1 << 25))
+    exp = oracle.sssp(row, col, wt, 3)
+    dist, st = ms.sssp(*dev_graph(row, col, wt), 3, delta=10_000_000, num_buckets=2)
+    np.testing.assert_array_equal(host(dist), exp)
+    assert st["max_pending"] > 4096 * 1024
+
+
 def test_sssp_bad_edge_is_reported():
     from paper_1701_01189_amd import binding as ms
     row, col, wt = csr(4, [0, 1, 2], [1, 2, 3], [1, 1, 1])
