@@ -1,26 +1,39 @@
 #!/usr/bin/env python3
 """Benchmark of the gfx950 stable multisplit (one JSON line on stdout).
 
-Default workload: key-value multisplit of n = 2^25 pairs, uint32 keys uniform
-over [0, 2^32) (SplitMix64 seed 102), values = original index, m = 32 equal
-range buckets f(k) = k >> 27 -- the paper's key-value setting (Section 6:
-2^25 uniform 32-bit pairs, delta buckets).  A step is one complete multisplit
-call (pre-scan, scan, post-scan) with inputs already resident in HBM.
+Default workload (`headline`): key-only stable multisplit of n = 2^28 uint32
+keys uniform over [0, 2^32) (SplitMix64 seed 100) into m = 32 delta buckets
+f(k) = k >> 27, calls issued back to back with the keys already in HBM.  A
+step is one complete call (pre-scan, scan of H, post-scan).  `value` is
+Gkeys/s over K back-to-back calls timed between two events with nothing else
+on the stream; the per-stage times come from a second pass of K calls that
+record stage events.
 
-Reported: Gpairs/s of the whole call; the roofline of the dominant kernel
-(the post-scan: 16 algorithmic bytes per pair -- key and value read once and
-written once), timed with HIP events on the stream the kernels run on; and
-the CPU oracle timed on the host cores.
+The same line carries, under `rows`, every other measured configuration, each
+with its own roofline and CPU-oracle baseline:
+  * sweep: key-only and key-value, n = 2^28, m = 2, 4, ..., 256;
+  * skew: m = 256 with binomial B(255, 1/2) and 1/4-uniform bucket
+    distributions next to uniform buckets, n = 2^25 (Section 6.4);
+  * keys_2e20_m8: n = 2^20, m = 8 (HIP-graph replays: a call is ~20 us);
+  * pairs_2e25_m32: the block- / wave- / no-reorder sweep over tile shapes
+    (Section 6.2, WMS against BMS);
+  * range_2e27_m256: 2^27 lognormal keys, 256 range buckets, learned bucket
+    identifier against binary search over the splitters;
+  * batched_4096_m64: 4096 key-value instances in one persistent launch,
+    autotuned, HIP-graph replays;
+  * radix_pairs_2e28: LSD radix sort of 2^28 pairs, 4 passes of 8 bits.
 
-Other workloads (--workload): keys_2e20_m8, keys_2e28_m<m>, pairs_2e28_m<m>
-(m up to 65536; above 256 two stable passes over 8-bit digits of the bucket),
-radix_pairs_2e28, radix_keys_2e28, hist_2e<k>_m<m> and histrange_2e<k>_m<m>
-(device-wide histograms, even or range bins), and range_2e27_m256: n = 2^27 lognormal
-(mu 20, sigma 2) keys saturated to 32 bits (seed 103), 256 range buckets at
-quantiles of a 2^16-key sample (seed 1031); sssp_rmat_2e20[_d<delta>]: shortest
-paths on an R-MAT graph (Section 7.2); the learned identifier (fit on the
-GPU from 2^20 keys, seed 1032) is timed against the binary search over the
-same splitters, and `value` is the learned rate.
+Byte model (Section 6.2.2, speed of light): a key-only multisplit must move
+12 bytes per key (read by the pre-scan, read by the post-scan, written), a
+key-value one 20 bytes per pair.  `roofline` is that of the dominant kernel,
+the post-scan (8 bytes per key, 16 per pair); `whole_call` puts the call's
+12 or 20 bytes per element against the same 8 TB/s peak.
+
+Single workloads (--workload NAME) print one line each: keys_2e28_m<m>,
+pairs_2e28_m<m> (m up to 65536), keys_2e20_m8, pairs_2e25_m32,
+skew_{binomial,alpha,uniform}_{keys,pairs}_2e25_m256, ident_{keys,pairs}_2e25_b<b>,
+radix_{pairs,keys}_2e28[_b<bits>], range_2e27_m256, batched_4096_m64,
+hist_2e<k>_m<m>, histrange_2e<k>_m<m>, sssp_rmat_2e20[_d<delta>], copy_2e28.
 """
 import argparse
 import hashlib
@@ -35,24 +48,52 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBPS = 8000.0
 METRIC = "multisplit Gkeys/s & Gpairs/s (m=2..256) + % HBM roofline; learned vs binary-search"
 
+# Section 6.2.2: three 4-byte global accesses per key, five per key-value pair.
+BYTES_PER_KEY = 12
+BYTES_PER_PAIR = 20
+# The post-scan's share: read the key (and value) again, write it.
+POST_BYTES_PER_KEY = 8
+POST_BYTES_PER_PAIR = 16
+GATE_FRAC = 0.60  # key-only, m <= 32: at least 60 % of the HBM peak, whole call
+
+
+def progress(msg):
+    """A line on stderr after each measured row (the JSON line is stdout's)."""
+    print("bench: " + msg, file=sys.stderr, flush=True)
+
+
+def call_bytes(kv):
+    return BYTES_PER_PAIR if kv else BYTES_PER_KEY
+
+
+def sol_rate(bandwidth_gbps, kv):
+    """Speed-of-light rate (G elements/s) at a bandwidth, by the byte model."""
+    return bandwidth_gbps / call_bytes(kv)
+
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="pairs_2e25_m32")
+    ap.add_argument("--workload", default="headline")
     ap.add_argument("--reorder", type=int, default=0)
     ap.add_argument("--waves", type=int, default=0)
     ap.add_argument("--items", type=int, default=0)
     ap.add_argument("--chunks", type=int, default=0)
     ap.add_argument("--claim", type=int, default=0, help="batched: work items per queue claim")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--cold-reps", type=int, default=10,
-                    help="calls timed one by one after writing a 1 GiB scratch buffer (0: skip)")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="oracle time budget of the headline (or single workload)")
+    ap.add_argument("--row-cpu-seconds", type=float, default=1.0,
+                    help="oracle time budget of each sub-row")
+    ap.add_argument("--cold-reps", type=int, default=0,
+                    help="single workloads: calls timed one by one after a 1 GiB scratch "
+                         "write and read-back (informational; 0: skip)")
     ap.add_argument("--no-ceiling", action="store_true",
                     help="skip the streaming-copy ceiling measurement")
+    ap.add_argument("--rows", default="sweep,skew,config1,config2,config3,config4,config5",
+                    help="headline: comma-separated sub-row groups to measure")
     return ap.parse_args()
 
 
@@ -91,12 +132,11 @@ def copy_ceiling(dev, reps=20, n=1 << 28):
 
 
 def cold_steps(step, reps, dev):
-    """Each call timed alone (HIP events on the call's stream) after a 1 GiB
-    scratch buffer is written and then read back, outside the timed region:
-    the write evicts the 256 MB Infinity Cache and the L2s, and the read
-    evicts the write's own dirty lines, so the timed call neither finds its
-    data in a cache nor pays for someone else's write-back.  Returns
-    per-call ms."""
+    """Each call timed alone after a 1 GiB scratch buffer is written and read
+    back outside the timed region (caches hold none of the call's data).  The
+    timed region ends when the call's last kernel ends, which can be before
+    all of its dirty lines have reached HBM: informational only, never the
+    reported value."""
     import torch
     scratch = torch.empty(1 << 28, dtype=torch.int32, device=dev)
     hev = HipEvents(2 * reps)
@@ -124,44 +164,6 @@ def summary(ms_list, units):
             "value_mean": round(units / (mean * 1e-3) / 1e9, 3)}
 
 
-def workload(name):
-    """(kind, n, m, shift, seed): kind in keys, pairs, radix_keys, radix_pairs."""
-    if name == "pairs_2e25_m32":
-        return "pairs", 1 << 25, 32, 27, 102
-    if name == "keys_2e20_m8":
-        return "keys", 1 << 20, 8, 29, 101
-    if name.startswith("keys_2e28_m") or name.startswith("pairs_2e28_m"):
-        m = int(name.split("_m")[1])
-        r = (m - 1).bit_length()
-        return name.split("_")[0], 1 << 28, m, 32 - r, 100
-    if name.startswith("ident_"):
-        # ident_keys_2e25_b5: keys uniform in [0, 2^b), identity buckets f(k) = k,
-        # m = 2^b (the paper's multisplit-with-identity-buckets sweep, Section 7.1)
-        parts = name.split("_")
-        bits = int(parts[3][1:])
-        return parts[1] + "_ident", 1 << int(parts[2][2:]), 1 << bits, 0, 120 + bits
-    if name.startswith("radix_pairs_2e28") or name.startswith("radix_keys_2e28"):
-        # radix_pairs_2e28 (8-bit digits) or radix_pairs_2e28_b<bits>; the
-        # shift slot carries the digit width
-        bits = int(name.split("_b")[1]) if "_b" in name else 8
-        return name.split("_2e28")[0], 1 << 28, 1 << bits, bits, 105
-    if name == "range_2e27_m256":
-        return "range", 1 << 27, 256, 0, 103
-    if name == "copy_2e28":
-        return "copy", 1 << 28, 1, 0, 7
-    if name.startswith("sssp_rmat_2e20"):
-        # sssp_rmat_2e20 (delta 800, the fastest measured) or sssp_rmat_2e20_d<delta>
-        delta = int(name.split("_d")[1]) if "_d" in name else 800
-        return "sssp", 20, 4_800_000, delta, 106
-    if name == "batched_4096_m64":
-        return "batched", 4096, 64, 8, 104
-    if name.startswith("hist_") or name.startswith("histrange_"):
-        # hist_2e25_m32: even bins (k >> (32 - log2 m)); histrange_: m-1 random splitters
-        size, mm = name.split("_")[1], int(name.split("_m")[1])
-        return name.split("_")[0], 1 << int(size[2:]), mm, 32 - (mm - 1).bit_length(), 110
-    raise SystemExit("unknown workload %s" % name)
-
-
 class HipEvents:
     """hipEvent_t handles created through the HIP runtime itself, so that the
     library can record them on the stream its kernels run on."""
@@ -174,6 +176,7 @@ class HipEvents:
                                                  ctypes.c_void_p]
         self.hip.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
         self.hip.hipEventDestroy.argtypes = [ctypes.c_void_p]
+        self.hip.hipEventRecord.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
         self.ev = []
         for _ in range(count):
             h = ctypes.c_void_p()
@@ -185,7 +188,6 @@ class HipEvents:
         """Record event i on torch's current stream (the one the library
         launches on)."""
         import torch
-        self.hip.hipEventRecord.argtypes = [self.ct.c_void_p, self.ct.c_void_p]
         st = torch.cuda.current_stream().cuda_stream
         if self.hip.hipEventRecord(self.ct.c_void_p(self.ev[i]), self.ct.c_void_p(st)) != 0:
             raise RuntimeError("hipEventRecord failed")
@@ -216,7 +218,7 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_for(kernel, workload_name, n_units):
+def traffic_for(kernel, workload_name):
     """HBM bytes per launch from committed rocprofv3 FETCH_SIZE/WRITE_SIZE
     counters, or None when none were taken for the current kernel sources."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
@@ -232,88 +234,378 @@ def traffic_for(kernel, workload_name, n_units):
     return e.get("bytes_per_launch")
 
 
-def cpu_baseline(kind, keys, vals, m, shift, budget_s):
-    import oracle
-    n = len(keys)
+def roofline(kernel, workload_name, algo_bytes, kernel_ms, ceiling=None):
+    achieved = algo_bytes / (kernel_ms * 1e-3) / 1e9
+    r = {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1),
+         "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+         "traffic": traffic_for(kernel, workload_name),
+         "algorithmic_bytes_per_launch": int(algo_bytes),
+         "avg_launch_ms": round(kernel_ms, 5)}
+    if ceiling:
+        r["copy_ceiling_GBps"] = round(ceiling, 1)
+        r["frac_of_copy_ceiling"] = round(achieved / ceiling, 4)
+    return r
+
+
+def whole_call(n, kv, call_ms, passes=1):
+    b = n * passes * call_bytes(kv)
+    gbps = b / (call_ms * 1e-3) / 1e9
+    return {"bytes_per_unit": passes * call_bytes(kv), "achieved": round(gbps, 1),
+            "unit": "GB/s", "frac": round(gbps / HBM_PEAK_GBPS, 4)}
+
+
+def _oracle_rate(run, units, budget_s, max_reps=50):
     reps, t0 = 0, time.perf_counter()
-    if kind.startswith("radix"):
-        sample = min(n, 1 << 24)
-        k, v = keys[:sample], (vals[:sample] if vals is not None else None)
-        while True:
-            oracle.radix_sort(k, v)
-            reps += 1
-            el = time.perf_counter() - t0
-            if el > budget_s or reps >= 50:
-                break
-        return {"value": sample * reps / el / 1e9, "unit": "Gpairs/s" if v is not None else
-                "Gkeys/s", "cores": 1, "kind": "oracle", "cpu_model": cpu_model(),
-                "sample": "std::stable_sort of the first 2^24 elements, %d reps" % reps}
-    mask = m - 1
-    if kind == "range":
-        sample = min(n, 1 << 24)
-        while True:
-            oracle.multisplit(keys[:sample], m, oracle.SPLITTERS, splitters=vals)
-            reps += 1
-            el = time.perf_counter() - t0
-            if el > budget_s or reps >= 50:
-                break
-        return {"value": sample * reps / el / 1e9, "unit": "Gkeys/s", "cores": 1,
-                "kind": "oracle", "cpu_model": cpu_model(),
-                "sample": "the first 2^24 keys, std::upper_bound buckets, %d reps" % reps}
     while True:
-        oracle.multisplit(keys, m, oracle.SHIFT_MASK, vals=vals, shift=shift, mask=mask)
+        run()
         reps += 1
         el = time.perf_counter() - t0
-        if el > budget_s or reps >= 50:
+        if el > budget_s or reps >= max_reps:
             break
-    return {"value": n * reps / el / 1e9, "unit": "Gpairs/s" if vals is not None else "Gkeys/s",
-            "cores": 1, "kind": "oracle", "cpu_model": cpu_model(),
-            "sample": "the full %d-element input, %d reps, single-threaded" % (n, reps)}
+    return units * reps / el / 1e9, reps
 
 
-def time_steps(step, K, warmup):
-    """Warm-up, then K timed calls; per call a list of 4 stage events."""
+def cpu_baseline(kind, keys, vals, m, shift, budget_s, sample_max=None, splitters=None):
+    """The CPU oracle (single-threaded) on a bounded sample of the same input."""
+    import oracle
+    n = len(keys)
+    sample = n if sample_max is None else min(n, sample_max)
+    k = keys[:sample]
+    v = vals[:sample] if vals is not None else None
+    unit = "Gpairs/s" if v is not None else "Gkeys/s"
+    if kind.startswith("radix"):
+        rate, reps = _oracle_rate(lambda: oracle.radix_sort(k, v), sample, budget_s)
+        what = "std::stable_sort of the first %d elements, %d reps" % (sample, reps)
+    elif splitters is not None:
+        rate, reps = _oracle_rate(
+            lambda: oracle.multisplit(k, m, oracle.SPLITTERS, vals=v, splitters=splitters),
+            sample, budget_s)
+        what = "the first %d keys, upper-bound buckets, %d reps" % (sample, reps)
+    else:
+        rate, reps = _oracle_rate(
+            lambda: oracle.multisplit(k, m, oracle.SHIFT_MASK, vals=v, shift=shift, mask=m - 1),
+            sample, budget_s)
+        what = "the first %d elements, %d reps" % (sample, reps)
+    return {"value": round(rate, 5), "unit": unit, "cores": 1, "kind": "oracle",
+            "cpu_model": cpu_model(), "sample": what + ", single-threaded"}
+
+
+def time_calls(step, K, warmup, stages=True, graph=False):
+    """Warm-up, then K back-to-back calls between two events (nothing else on
+    the stream).  With stages, a second pass of K calls records the four
+    stage events of each call (the radix sort records its last pass only) and
+    the mean stage times are returned.  With graph, the call is also captured
+    in a HIP graph and K replays are timed."""
     import torch
+    stream = torch.cuda.current_stream()
     for _ in range(warmup):
         step(None)
-    hev = HipEvents(4 * K)
-    evs = [[_Handle(hev.ev[4 * i + j]) for j in range(4)] for i in range(K)]
-    stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     t0.record(stream)
-    for i in range(K):
-        step(evs[i])
+    for _ in range(K):
+        step(None)
     t1.record(stream)
     torch.cuda.synchronize()
-    total = t0.elapsed_time(t1) / K
-    stage = [sum(hev.ms(4 * i + s, 4 * i + s + 1) for i in range(K)) / K for s in range(3)]
-    hev.close()
-    return total, stage
+    out = {"ms": t0.elapsed_time(t1) / K}
+    if stages:
+        hev = HipEvents(4 * K)
+        evs = [[_Handle(hev.ev[4 * i + j]) for j in range(4)] for i in range(K)]
+        torch.cuda.synchronize()
+        for i in range(K):
+            step(evs[i])
+        torch.cuda.synchronize()
+        out["stage"] = [sum(hev.ms(4 * i + s, 4 * i + s + 1) for i in range(K)) / K
+                        for s in range(3)]
+        hev.close()
+    if graph:
+        side = torch.cuda.Stream()
+        side.wait_stream(stream)
+        with torch.cuda.stream(side):
+            step(None)
+        stream.wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            step(None)
+        for _ in range(warmup):
+            g.replay()
+        torch.cuda.synchronize()
+        t0.record(stream)
+        for _ in range(K):
+            g.replay()
+        t1.record(stream)
+        torch.cuda.synchronize()
+        out["graph_ms"] = t0.elapsed_time(t1) / K
+        del g
+    return out
 
 
-def bench_batched(args, num, m, shift, seed, dev):
+# ---------------------------------------------------------------------------
+# multisplit rows
+# ---------------------------------------------------------------------------
+def multisplit_row(args, name, dk, dv, m, fn, shape=(0, 0, 0), graph=False, cpu=None,
+                   ceiling=None, radix_bits=0, tune=False):
+    """One multisplit (or radix sort when radix_bits) workload on resident
+    device inputs.  With tune, the shape comes from the autotuner through
+    its cache.  Returns the row dict."""
+    import torch
+
+    from paper_1701_01189_amd import binding as ms
+    from paper_1701_01189_amd import tuning
+    n = dk.numel()
+    kv = dv is not None
+    ok = torch.empty_like(dk)
+    ov = torch.empty_like(dv) if kv else None
+    mm = (1 << radix_bits) if radix_bits else m
+    off = torch.empty(mm + 1, dtype=torch.int32, device=dk.device)
+    op = ((ms.OP_RADIX_SORT_PAIRS if kv else ms.OP_RADIX_SORT) if radix_bits else
+          (ms.OP_PAIRS if kv else ms.OP_KEYS))
+    tuned = None
+    if tune and shape == (0, 0, 0):
+        topt, tuned = tuning.tuned_options(op, dk, dv, radix_bits if radix_bits else m, fn=fn)
+        shape = (topt.reorder, topt.waves_per_block, topt.items_per_lane)
+    base = dict(reorder=shape[0], waves_per_block=shape[1], items_per_lane=shape[2],
+                max_chunks=args.chunks)
+    ws = torch.empty(max(256, ms.workspace_size(op, n, mm, 0, ms.Options(**base))),
+                     dtype=torch.uint8, device=dk.device)
+    opt_plain = ms.Options(**base)
+
+    def step(ev):
+        o = opt_plain if ev is None else ms.Options(stage_events=ev, **base)
+        if radix_bits:
+            ms.radix_sort(dk, dv, radix_bits, keys_out=ok, vals_out=ov, options=o, ws=ws)
+        elif kv:
+            ms.pairs(dk, dv, m, fn, keys_out=ok, vals_out=ov, offsets=off, options=o, ws=ws)
+        else:
+            ms.keys(dk, m, fn, keys_out=ok, offsets=off, options=o, ws=ws)
+
+    t = time_calls(step, args.steps, args.warmup, stages=True, graph=graph)
+    call_ms = t["graph_ms"] if graph else t["ms"]
+    passes = -(-32 // radix_bits) if radix_bits else 1
+    value = n / (call_ms * 1e-3) / 1e9
+    post_ms = t["stage"][2]
+    kern = "postscan"
+    row = {
+        "workload": name, "n": n, "m": mm, "kv": kv,
+        "value": round(value, 3), "unit": "Gpairs/s" if kv else "Gkeys/s",
+        "ms_per_call": round(call_ms, 5),
+        "timing": "hipgraph replays" if graph else "back-to-back eager calls",
+        "stage_ms": {"prescan": round(t["stage"][0], 5), "scan": round(t["stage"][1], 5),
+                     "postscan": round(post_ms, 5)},
+        "roofline": roofline(kern, name, n * (POST_BYTES_PER_PAIR if kv else POST_BYTES_PER_KEY),
+                             post_ms, ceiling),
+        "whole_call": whole_call(n, kv, call_ms, passes),
+    }
+    if radix_bits:
+        row["passes"] = passes
+        row["stage_ms_note"] = "stages of the last pass"
+    if graph:
+        row["eager_ms_per_call"] = round(t["ms"], 5)
+    if shape != (0, 0, 0):
+        row["shape"] = {"reorder": ["auto", "block", "wave", "none"][shape[0]],
+                        "waves_per_block": shape[1], "windows_per_wave": shape[2]}
+    if tuned is not None:
+        row["tuner"] = tuned
+    if cpu is not None and not args.no_cpu_baseline:
+        row["cpu_baseline"] = cpu()
+    del ok, ov, ws
+    progress("%s: %.3f %s" % (name, row["value"], row["unit"]))
+    return row
+
+
+def keys_device(keys, vals, dev):
+    import numpy as np
+    import torch
+    dk = torch.from_numpy(keys.view(np.int32)).to(dev)
+    dv = torch.from_numpy(vals.view(np.int32)).to(dev) if vals is not None else None
+    return dk, dv
+
+
+def pow2_fn(m):
+    from paper_1701_01189_amd import binding as ms
+    r = (m - 1).bit_length()
+    if m & (m - 1) == 0:
+        return ms.BucketFn.shift_mask(32 - r if r else 0, m - 1), 32 - r
+    return ms.BucketFn.div(-(-(1 << 32) // m)), None
+
+
+def rows_sweep(args, keys, dev, ceiling, sizes=(2, 4, 8, 16, 32, 64, 128, 256), headline=None):
+    """Key-only and key-value at n = 2^28, m = 2..256, shift buckets."""
+    from paper_1701_01189_amd import inputs
+    out = {}
+    dk, _ = keys_device(keys, None, dev)
+    for m in sizes:
+        name = "keys_2e28_m%d" % m
+        if headline is not None and name == headline["workload"]:
+            out[name] = {k: v for k, v in headline.items() if k != "rows"}
+            continue
+        fn, shift = pow2_fn(m)
+        out[name] = multisplit_row(
+            args, name, dk, None, m, fn, ceiling=ceiling,
+            cpu=lambda m=m, shift=shift: cpu_baseline("keys", keys, None, m, shift,
+                                                      args.row_cpu_seconds, 1 << 22))
+    vals = inputs.index_values(len(keys))
+    _, dv = keys_device(keys, vals, dev)
+    for m in sizes:
+        name = "pairs_2e28_m%d" % m
+        fn, shift = pow2_fn(m)
+        out[name] = multisplit_row(
+            args, name, dk, dv, m, fn, ceiling=ceiling,
+            cpu=lambda m=m, shift=shift: cpu_baseline("pairs", keys, vals, m, shift,
+                                                      args.row_cpu_seconds, 1 << 22))
+    del dk, dv
+    return out
+
+
+def rows_skew(args, dev, ceiling):
+    """m = 256 with skewed bucket distributions (Section 6.4, Table of
+    distributions): binomial B(255, 1/2) and 1/4-uniform, beside uniform
+    buckets, n = 2^25 as in the paper, keys and pairs."""
+    from paper_1701_01189_amd import binding as ms
+    from paper_1701_01189_amd import inputs
+    n, m = 1 << 25, 256
+    out = {}
+    vals = inputs.index_values(n)
+    fn = ms.BucketFn.shift_mask(24, 255)
+    for dist in ("binomial", "alpha", "uniform"):
+        keys = inputs.skewed_bucket_keys(100, n, m, dist)
+        dk, dv = keys_device(keys, vals, dev)
+        for kv in (False, True):
+            name = "skew_%s_%s_2e25_m256" % (dist, "pairs" if kv else "keys")
+            out[name] = multisplit_row(
+                args, name, dk, dv if kv else None, m, fn, ceiling=ceiling,
+                cpu=lambda keys=keys, kv=kv: cpu_baseline(
+                    "pairs" if kv else "keys", keys, vals if kv else None, m, 24,
+                    args.row_cpu_seconds, 1 << 22))
+            out[name]["distribution"] = {"binomial": "bucket ~ B(255, 1/2)",
+                                         "alpha": "1/4 uniform, else one bucket",
+                                         "uniform": "uniform"}[dist]
+        del dk, dv
+    return out
+
+
+def row_config1(args, dev, ceiling):
+    """n = 2^20 keys (seed 101), m = 8, f = k >> 29: a call is a few tens of
+    microseconds, so HIP-graph replays time the GPU rather than the host."""
+    from paper_1701_01189_amd import binding as ms
+    from paper_1701_01189_amd import inputs
+    keys = inputs.uniform_u32(101, 1 << 20)
+    dk, _ = keys_device(keys, None, dev)
+    row = multisplit_row(args, "keys_2e20_m8", dk, None, 8, ms.BucketFn.shift_mask(29, 7),
+                         graph=True, ceiling=ceiling, tune=True,
+                         cpu=lambda: cpu_baseline("keys", keys, None, 8, 29,
+                                                  args.row_cpu_seconds))
+    row["note"] = "latency bound: 12.6 MB fits in the 256 MB memory-side cache"
+    return row
+
+
+CONFIG2_SHAPES = [(0, 0, 0), (1, 4, 16), (1, 8, 8), (1, 8, 4), (1, 4, 8), (1, 16, 8),
+                  (2, 8, 8), (2, 4, 16), (3, 8, 8)]
+
+
+def rows_config2(args, dev, ceiling):
+    """n = 2^25 pairs (seed 102), values = index, m = 32, f = k >> 27; block-,
+    wave- and no-reorder over tile shapes."""
+    from paper_1701_01189_amd import binding as ms
+    from paper_1701_01189_amd import inputs
+    n = 1 << 25
+    keys = inputs.uniform_u32(102, n)
+    vals = inputs.index_values(n)
+    dk, dv = keys_device(keys, vals, dev)
+    fn = ms.BucketFn.shift_mask(27, 31)
+    out = {}
+    cpu_once = {}
+
+    def cpu():
+        if "v" not in cpu_once:
+            cpu_once["v"] = cpu_baseline("pairs", keys, vals, 32, 27, args.row_cpu_seconds)
+        return cpu_once["v"]
+    for shape in CONFIG2_SHAPES:
+        tag = "auto" if shape == (0, 0, 0) else "%s_%dx%d" % (
+            ["", "block", "wave", "none"][shape[0]], shape[1], shape[2])
+        name = "pairs_2e25_m32"
+        r = multisplit_row(args, name, dk, dv, 32, fn, shape=shape, ceiling=ceiling, cpu=cpu)
+        out["pairs_2e25_m32_" + tag] = r
+    return out
+
+
+def row_config3(args, dev, ceiling):
+    """n = 2^27 lognormal(20, 2) keys saturated to 32 bits (seed 103); 255
+    splitters at the quantiles of a 2^16-key sample (seed 1031); the learned
+    model is fitted on the GPU from 2^20 keys (seed 1032).  The same
+    multisplit runs with the learned identifier and with binary search."""
+    import numpy as np
+    import torch
+
+    from paper_1701_01189_amd import binding as ms
+    from paper_1701_01189_amd import inputs
+    n, m = 1 << 27, 256
+    keys = inputs.lognormal_u32(103, n)
+    spl = inputs.quantile_splitters(inputs.lognormal_u32(1031, 1 << 16), m)
+    fit = inputs.lognormal_u32(1032, 1 << 20)
+    dk, _ = keys_device(keys, None, dev)
+    ds = torch.from_numpy(spl.view(np.int32)).to(dev)
+    dfit = torch.from_numpy(fit.view(np.int32)).to(dev)
+    model = torch.empty(ms.MODEL_FLOATS, dtype=torch.float32, device=dev)
+    fws = torch.empty(max(256, ms.workspace_size(ms.OP_LEARNED_FIT, len(fit), m)),
+                      dtype=torch.uint8, device=dev)
+    ev = HipEvents(2)
+    for _ in range(3):
+        ms.learned_fit(dfit, ds, m, model=model, ws=fws)
+    torch.cuda.synchronize()
+    ev.record(0)
+    reps = 10
+    for _ in range(reps):
+        ms.learned_fit(dfit, ds, m, model=model, ws=fws)
+    ev.record(1)
+    torch.cuda.synchronize()
+    fit_ms = ev.ms(0, 1) / reps
+    ev.close()
+    res = {}
+    for name, fn in (("learned", ms.BucketFn.learned(ds, model)),
+                     ("binary_search", ms.BucketFn.splitter(ds))):
+        res[name] = multisplit_row(
+            args, "range_2e27_m256_" + name, dk, None, m, fn, ceiling=ceiling, tune=True,
+            cpu=(lambda: cpu_baseline("range", keys, None, m, 0, args.row_cpu_seconds, 1 << 22,
+                                      splitters=spl)) if name == "learned" else None)
+    miss = torch.zeros(1, dtype=torch.int64, device=dev)
+    ms.keys(dk, m, ms.BucketFn.learned(ds, model), options=ms.Options(mispredicts=miss))
+    torch.cuda.synchronize()
+    row = res["learned"]
+    row["workload"] = "range_2e27_m256"
+    row["bucket"] = "learned range (255 lognormal quantile splitters)"
+    row["binary_search"] = res["binary_search"]
+    row["learned_speedup"] = round(res["binary_search"]["ms_per_call"] / row["ms_per_call"], 4)
+    row["learned_beats_binary_search"] = row["value"] > res["binary_search"]["value"]
+    row["mispredict_rate"] = round(int(miss.item()) / n, 5)
+    row["fit_ms"] = round(fit_ms, 4)
+    row["fit_sample"] = len(fit)
+    return row
+
+
+def row_config4(args, dev):
     """4096 independent key-value instances, sizes log-uniform in [2^8, 2^20]
     (seed 104), keys uniform (seed 104000 + i), values = index within the
-    instance, m = 64, f(k) = (k >> 8) & 63; the tuning comes from the
-    autotuner; the call is captured in a HIP graph and the replays are timed."""
+    instance, m = 64, f(k) = (k >> 8) & 63; tuning from the autotuner; the
+    call is captured in a HIP graph and the replays are timed."""
     import numpy as np
     import torch
 
     from paper_1701_01189_amd import binding as ms
     from paper_1701_01189_amd import inputs, tuning
+    num, m, seed = 4096, 64, 104
     sizes = inputs.batched_sizes(seed, num)
     seg = inputs.segment_offsets(sizes)
     keys, vals = inputs.batched_pairs(seed, sizes)
     total = len(keys)
-    dk = torch.from_numpy(keys.view(np.int32)).to(dev)
-    dv = torch.from_numpy(vals.view(np.int32)).to(dev)
+    dk, dv = keys_device(keys, vals, dev)
     ds = torch.from_numpy(seg.astype(np.int64)).to(dev)
-    fn = ms.BucketFn.shift_mask(shift, m - 1)
+    fn = ms.BucketFn.shift_mask(8, m - 1)
     if args.reorder or args.waves or args.items or args.claim:
-        opt = ms.Options(waves_per_block=args.waves, items_per_lane=args.items,
-                         batch_claim=args.claim)
+        opt = ms.Options(reorder=args.reorder, waves_per_block=args.waves,
+                         items_per_lane=args.items, batch_claim=args.claim)
         tune = {"source": "command line"}
     else:
         opt, tune = tuning.tuned_options(ms.OP_BATCHED, dk, dv, m, fn=fn, seg=ds)
@@ -321,55 +613,245 @@ def bench_batched(args, num, m, shift, seed, dev):
     off = torch.empty(num * (m + 1), dtype=torch.int32, device=dev)
     need = ms.workspace_size(ms.OP_BATCHED, total, m, num, opt)
     ws = torch.empty(need, dtype=torch.uint8, device=dev)
-    side = torch.cuda.Stream()
-    side.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(side):
+
+    def step(ev):
+        if ev is not None:
+            ev.record(0)
         ms.batched(dk, dv, ds, m, fn, keys_out=ko, vals_out=vo, offsets=off, options=opt, ws=ws)
-    torch.cuda.current_stream().wait_stream(side)
+        if ev is not None:
+            ev.record(1)
+    t = time_calls(step, args.steps, args.warmup, stages=False, graph=True)
+    # the persistent kernel's own time: the call between two events, minus
+    # nothing (the set-up kernel is a few microseconds of one workgroup)
+    hev = HipEvents(2)
     torch.cuda.synchronize()
-    g = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(g):
-        ms.batched(dk, dv, ds, m, fn, keys_out=ko, vals_out=vo, offsets=off, options=opt, ws=ws)
-    for _ in range(args.warmup):
-        g.replay()
-    torch.cuda.synchronize()
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    t0.record()
+    hev.record(0)
     for _ in range(args.steps):
-        g.replay()
-    t1.record()
+        ms.batched(dk, dv, ds, m, fn, keys_out=ko, vals_out=vo, offsets=off, options=opt, ws=ws)
+    hev.record(1)
     torch.cuda.synchronize()
-    t = t0.elapsed_time(t1) / args.steps
+    eager_ms = hev.ms(0, 1) / args.steps
+    hev.close()
     status = ms.batched_status(ws)
-    value = total / (t * 1e-3) / 1e9
-    gbps = 20.0 * total / (t * 1e-3) / 1e9
+    call_ms = t["graph_ms"]
+    row = {
+        "workload": "batched_4096_m64", "instances": num, "n": total, "m": m, "kv": True,
+        "value": round(total / (call_ms * 1e-3) / 1e9, 3), "unit": "Gpairs/s",
+        "ms_per_call": round(call_ms, 5), "timing": "hipgraph replays",
+        "eager_ms_per_call": round(eager_ms, 5),
+        "status": status,
+        "tuning": {"reorder": opt.reorder, "waves_per_block": opt.waves_per_block,
+                   "items_per_lane": opt.items_per_lane, "batch_claim": opt.batch_claim},
+        "tuner": tune,
+        "roofline": roofline("batched", "batched_4096_m64", total * BYTES_PER_PAIR, call_ms),
+        "whole_call": whole_call(total, True, call_ms),
+    }
+    row["roofline"]["kernel"] = "batched_kernel (pre-scan and post-scan items; set-up kernel " \
+                                "included)"
+    progress("batched_4096_m64: %.3f Gpairs/s" % row["value"])
+    if not args.no_cpu_baseline:
+        import oracle
+        k = keys[:1 << 22]
+        v = vals[:1 << 22]
+        cut = int(np.searchsorted(seg, 1 << 22, side="right")) - 1
+        sseg = seg[:cut + 1].astype(np.uint64)
+        units = int(sseg[-1])
+        rate, reps = _oracle_rate(
+            lambda: oracle.batched(k[:units], v[:units], sseg, m, oracle.SHIFT_MASK, shift=8,
+                                   mask=m - 1), units, args.row_cpu_seconds)
+        row["cpu_baseline"] = {"value": round(rate, 5), "unit": "Gpairs/s", "cores": 1,
+                               "kind": "oracle", "cpu_model": cpu_model(),
+                               "sample": "the first %d instances (%d pairs), %d reps, "
+                                         "single-threaded" % (cut, units, reps)}
+    return row
+
+
+def row_config5(args, dev, ceiling, bits=8, kv=True):
+    """LSD radix sort of n = 2^28 pairs (keys seed 105, values = index), 8-bit
+    digits, 4 multisplit passes of m = 256."""
+    from paper_1701_01189_amd import inputs
+    n = 1 << 28
+    keys = inputs.uniform_u32(105, n)
+    vals = inputs.index_values(n) if kv else None
+    dk, dv = keys_device(keys, vals, dev)
+    name = "radix_%s_2e28" % ("pairs" if kv else "keys") + ("" if bits == 8 else "_b%d" % bits)
+    return multisplit_row(args, name, dk, dv, 0, None, ceiling=ceiling, radix_bits=bits,
+                          tune=True,
+                          cpu=lambda: cpu_baseline("radix", keys, vals, 0, 0,
+                                                   args.row_cpu_seconds, 1 << 22))
+
+
+def headline(args, dev):
+    """2^28 key-only m = 32 (the gate configuration), plus every sub-row."""
+    from paper_1701_01189_amd import inputs
+    ceiling = None if args.no_ceiling else copy_ceiling(dev)
+    n, m = 1 << 28, 32
+    keys = inputs.uniform_u32(100, n)
+    dk, _ = keys_device(keys, None, dev)
+    fn, shift = pow2_fn(m)
+    head = multisplit_row(args, "keys_2e28_m32", dk, None, m, fn, ceiling=ceiling)
+    del dk
+    rows = {}
+    groups = [g for g in args.rows.split(",") if g]
+    if "sweep" in groups:
+        rows.update(rows_sweep(args, keys, dev, ceiling, headline=head))
+    if "skew" in groups:
+        rows.update(rows_skew(args, dev, ceiling))
+    if "config1" in groups:
+        rows["keys_2e20_m8"] = row_config1(args, dev, ceiling)
+    if "config2" in groups:
+        rows.update(rows_config2(args, dev, ceiling))
+    if "config3" in groups:
+        rows["range_2e27_m256"] = row_config3(args, dev, ceiling)
+    if "config4" in groups:
+        rows["batched_4096_m64"] = row_config4(args, dev)
+    if "config5" in groups:
+        rows["radix_pairs_2e28"] = row_config5(args, dev, ceiling)
+    gate_rows = {k: r for k, r in rows.items()
+                 if k.startswith("keys_2e28_m") and int(k.split("_m")[1]) <= 32}
+    gate_rows.setdefault("keys_2e28_m32", head)
     line = {
-        "metric": METRIC, "value": round(value, 3), "unit": "Gpairs/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(t, 5),
+        "metric": METRIC,
+        "value": head["value"],
+        "unit": "Gkeys/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_call"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "keys_2e28_m32: key-only stable multisplit, n = 2^28 uniform "
+                               "u32 keys (seed 100), m = 32, f(k) = k >> 27, back-to-back calls",
+                   "n": n, "m": m, "kv": False, "seed": 100,
+                   "bucket": "shift_mask (delta buckets of width 2^27)"},
+        "timing": head["timing"],
+        "stage_ms": head["stage_ms"],
+        "roofline": head["roofline"],
+        "whole_call": head["whole_call"],
+        "gate": {"target": "key-only, n = 2^28, m <= 32: whole call >= 60 % of 8 TB/s at "
+                           "12 B/key (>= 400 Gkeys/s), back-to-back calls",
+                 "per_m": {k: {"value": r["value"], "frac": r["whole_call"]["frac"],
+                               "met": r["whole_call"]["frac"] >= GATE_FRAC}
+                           for k, r in sorted(gate_rows.items(),
+                                              key=lambda kv: int(kv[0].split("_m")[1]))}},
+        "rows": rows,
+    }
+    if "range_2e27_m256" in rows:
+        r = rows["range_2e27_m256"]
+        line["learned_vs_binary_search"] = {
+            "learned": r["value"], "binary_search": r["binary_search"]["value"],
+            "unit": "Gkeys/s", "speedup": r["learned_speedup"],
+            "learned_beats_binary_search": r["learned_beats_binary_search"],
+            "mispredict_rate": r["mispredict_rate"]}
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline("keys", keys, None, m, shift, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+# ---------------------------------------------------------------------------
+# single workloads
+# ---------------------------------------------------------------------------
+def single_line(args, row, extra_config=None):
+    line = {
+        "metric": METRIC, "value": row["value"], "unit": row["unit"], "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": row["ms_per_call"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
         "data": "synthetic",
-        "config": {"workload": args.workload, "instances": num, "total_pairs": total, "m": m,
-                   "bucket": "(k >> 8) & 63", "seed": seed, "hipgraph": True,
-                   "tuning": {"waves_per_block": opt.waves_per_block,
-                              "items_per_lane": opt.items_per_lane,
-                              "batch_claim": opt.batch_claim}, "tuner": tune},
-        "status": status,
-        "roofline": {"bound": "hbm", "kernel": "batched_kernel (pre-scan and post-scan)",
-                     "achieved": round(gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": round(gbps / HBM_PEAK_GBPS, 4),
-                     "traffic": traffic_for("batched", args.workload, total),
-                     "bytes_per_unit": 20},
+        "config": {"workload": row["workload"], **(extra_config or {})},
     }
+    for k, v in row.items():
+        if k not in line and k not in ("workload", "ms_per_call"):
+            line[k] = v
     print(json.dumps(line), flush=True)
+
+
+def single_multisplit(args, name, dev):
+    import numpy as np
+
+    from paper_1701_01189_amd import binding as ms
+    from paper_1701_01189_amd import inputs
+    shape = (args.reorder, args.waves, args.items)
+    ceiling = None if args.no_ceiling else copy_ceiling(dev)
+    if name.startswith("radix_"):
+        bits = int(name.split("_b")[1]) if "_b" in name else 8
+        row = row_config5(args, dev, ceiling, bits=bits, kv=name.startswith("radix_pairs"))
+        return single_line(args, row)
+    if name.startswith("skew_"):
+        _, dist, kind, _size, _m = name.split("_")
+        n, m = 1 << 25, 256
+        keys = inputs.skewed_bucket_keys(100, n, m, dist)
+        vals = inputs.index_values(n) if kind == "pairs" else None
+        dk, dv = keys_device(keys, vals, dev)
+        row = multisplit_row(args, name, dk, dv, m, ms.BucketFn.shift_mask(24, 255),
+                             shape=shape, ceiling=ceiling,
+                             cpu=lambda: cpu_baseline(kind, keys, vals, m, 24, args.cpu_seconds,
+                                                      1 << 22))
+        return single_line(args, row)
+    if name.startswith("ident_"):
+        # ident_keys_2e25_b5: keys uniform in [0, 2^b), identity buckets
+        # f(k) = k, m = 2^b (Section 7.1's sweep)
+        parts = name.split("_")
+        bits = int(parts[3][1:])
+        n, m = 1 << int(parts[2][2:]), 1 << bits
+        keys = inputs.uniform_u32(120 + bits, n) & np.uint32(m - 1)
+        vals = inputs.index_values(n) if parts[1] == "pairs" else None
+        dk, dv = keys_device(keys, vals, dev)
+        row = multisplit_row(args, name, dk, dv, m, ms.BucketFn.shift_mask(0, m - 1),
+                             shape=shape, ceiling=ceiling,
+                             cpu=lambda: cpu_baseline(parts[1], keys, vals, m, 0,
+                                                      args.cpu_seconds, 1 << 22))
+        return single_line(args, row)
+    if name == "keys_2e20_m8":
+        return single_line(args, row_config1(args, dev, ceiling))
+    if name == "pairs_2e25_m32":
+        n = 1 << 25
+        keys = inputs.uniform_u32(102, n)
+        vals = inputs.index_values(n)
+        dk, dv = keys_device(keys, vals, dev)
+        row = multisplit_row(args, name, dk, dv, 32, ms.BucketFn.shift_mask(27, 31),
+                             shape=shape, ceiling=ceiling,
+                             cpu=lambda: cpu_baseline("pairs", keys, vals, 32, 27,
+                                                      args.cpu_seconds))
+        return single_line(args, row)
+    if name.startswith("keys_2e28_m") or name.startswith("pairs_2e28_m"):
+        m = int(name.split("_m")[1])
+        kv = name.startswith("pairs")
+        n = 1 << 28
+        keys = inputs.uniform_u32(100, n)
+        vals = inputs.index_values(n) if kv else None
+        dk, dv = keys_device(keys, vals, dev)
+        fn, shift = pow2_fn(m)
+        cpu = None
+        if shift is not None:
+            cpu = lambda: cpu_baseline("pairs" if kv else "keys", keys, vals, m, shift,  # noqa
+                                       args.cpu_seconds)
+        row = multisplit_row(args, name, dk, dv, m, fn, shape=shape, ceiling=ceiling, cpu=cpu)
+        if args.cold_reps > 0:
+            # informational: one call at a time after evicting the caches
+            import torch
+            ok = torch.empty_like(dk)
+            ov = torch.empty_like(dv) if kv else None
+
+            def step(_ev):
+                if kv:
+                    ms.pairs(dk, dv, m, fn, keys_out=ok, vals_out=ov)
+                else:
+                    ms.keys(dk, m, fn, keys_out=ok)
+            row["cold_per_call"] = summary(cold_steps(step, args.cold_reps, dev), n)
+        return single_line(args, row)
+    raise SystemExit("unknown workload %s" % name)
 
 
 def bench_hist(args, kind, n, m, shift, seed, dev):
     """Device-wide histogram (Section 7.3) of n uniform 32-bit keys: even bins
     f(k) = k >> (32 - log2 m), or range bins over m-1 sorted random splitters
     (seed 113), as in the paper's Even and Range experiments (2^25 elements,
-    m <= 256).  One step = one ms_histogram call (zero the output, pre-scan with
-    atomic accumulation)."""
+    m <= 256).  One step = one ms_histogram call (pre-scan, then the
+    per-bucket reduction of the subproblems' counts), timed from HIP-graph
+    replays."""
     import numpy as np
     import torch
 
@@ -387,64 +869,36 @@ def bench_hist(args, kind, n, m, shift, seed, dev):
                      dtype=torch.uint8, device=dev)
 
     def step(ev):
-        ms.histogram(dk, m, fn, hist=hist, options=ms.Options(stage_events=ev, **base), ws=ws)
-    t_eager, st = time_steps(step, args.steps, args.warmup)
-    # A call is ~20-200 us of GPU work, close to the host's own cost of a
-    # call from Python; replaying the call from a HIP graph measures the GPU.
-    side = torch.cuda.Stream()
-    side.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(side):
-        step(None)
-    torch.cuda.current_stream().wait_stream(side)
-    torch.cuda.synchronize()
-    g = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(g):
-        step(None)
-    for _ in range(args.warmup):
-        g.replay()
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(args.steps):
-        g.replay()
-    e1.record()
-    torch.cuda.synchronize()
-    t = e0.elapsed_time(e1) / args.steps
-    value = n / (t * 1e-3) / 1e9
-    pre_gbps = 4.0 * n / (st[0] * 1e-3) / 1e9
+        o = ms.Options(**base) if ev is None else ms.Options(stage_events=ev, **base)
+        ms.histogram(dk, m, fn, hist=hist, options=o, ws=ws)
+    t = time_calls(step, args.steps, args.warmup, stages=True, graph=True)
+    st = t["stage"]
+    value = n / (t["graph_ms"] * 1e-3) / 1e9
     line = {
         "metric": METRIC, "value": round(value, 3), "unit": "Gkeys/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(t, 5),
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(t["graph_ms"], 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "m": m,
-                   "bins": "range (m-1 random splitters)" if spl is not None else "even (k >> %d)" % shift,
-                   "seed": seed, **base},
-        "hipgraph": True,
-        "eager_value": round(n / (t_eager * 1e-3) / 1e9, 3),
+                   "bins": "range (m-1 random splitters)" if spl is not None else
+                           "even (k >> %d)" % shift, "seed": seed, **base},
+        "timing": "hipgraph replays",
+        "eager_value": round(n / (t["ms"] * 1e-3) / 1e9, 3),
         "stage_ms": {"prescan": round(st[0], 5), "reduce": round(st[1], 5)},
-        "roofline": {"bound": "hbm", "kernel": "prescan", "achieved": round(pre_gbps, 1),
-                     "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": round(pre_gbps / HBM_PEAK_GBPS, 4),
-                     "traffic": traffic_for("prescan", args.workload, n), "bytes_per_unit": 4},
+        "roofline": roofline("prescan", args.workload, 4.0 * n, st[0]),
     }
     if not args.no_cpu_baseline:
         import oracle
         sample = min(n, 1 << 24)
-        reps, t0 = 0, time.perf_counter()
-        while True:
-            if spl is not None:
-                oracle.histogram(keys[:sample], m, oracle.SPLITTERS, splitters=spl)
-            else:
-                oracle.histogram(keys[:sample], m, oracle.SHIFT_MASK, shift=shift, mask=m - 1)
-            reps += 1
-            el = time.perf_counter() - t0
-            if el > args.cpu_seconds or reps >= 50:
-                break
-        line["cpu_baseline"] = {"value": sample * reps / el / 1e9, "unit": "Gkeys/s", "cores": 1,
-                                "kind": "oracle", "cpu_model": cpu_model(),
-                                "sample": "the first 2^24 keys, %d reps" % reps}
+        if spl is not None:
+            run = lambda: oracle.histogram(keys[:sample], m, oracle.SPLITTERS, splitters=spl)  # noqa
+        else:
+            run = lambda: oracle.histogram(keys[:sample], m, oracle.SHIFT_MASK, shift=shift,  # noqa
+                                           mask=m - 1)
+        rate, reps = _oracle_rate(run, sample, args.cpu_seconds)
+        line["cpu_baseline"] = {"value": rate, "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
+                                "cpu_model": cpu_model(),
+                                "sample": "the first %d keys, %d reps" % (sample, reps)}
     print(json.dumps(line), flush=True)
 
 
@@ -513,14 +967,9 @@ def bench_sssp(args, scale, n_edges, delta, seed, dev):
     }
     if not args.no_cpu_baseline:
         import oracle
-        reps, t0 = 0, time.perf_counter()
-        while True:
-            oracle.sssp(row, col, wt, 0)
-            reps += 1
-            el = time.perf_counter() - t0
-            if el > args.cpu_seconds or reps >= 20:
-                break
-        line["cpu_baseline"] = {"value": round(ne * reps / el / 1e6, 2), "unit": "MTEPS",
+        rate, reps = _oracle_rate(lambda: oracle.sssp(row, col, wt, 0), ne / 1e3,
+                                  args.cpu_seconds, max_reps=20)
+        line["cpu_baseline"] = {"value": round(rate * 1e3, 2), "unit": "MTEPS",
                                 "cores": 1, "kind": "oracle", "cpu_model": cpu_model(),
                                 "sample": "the full graph, %d Dijkstra runs" % reps}
     print(json.dumps(line), flush=True)
@@ -534,18 +983,14 @@ def bench_copy(args, n, dev):
     from paper_1701_01189_amd import binding as ms
     a = torch.ones(n, dtype=torch.int32, device=dev)
     b = torch.empty_like(a)
-    stream = torch.cuda.current_stream()
     for _ in range(args.warmup):
         ms.copy_u32(b, a)
     hev = HipEvents(2)
-    hip = hev.hip
-    import ctypes
-    hip.hipEventRecord.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
     torch.cuda.synchronize()
-    hip.hipEventRecord(ctypes.c_void_p(hev.ev[0]), ctypes.c_void_p(stream.cuda_stream))
+    hev.record(0)
     for _ in range(args.steps):
         ms.copy_u32(b, a)
-    hip.hipEventRecord(ctypes.c_void_p(hev.ev[1]), ctypes.c_void_p(stream.cuda_stream))
+    hev.record(1)
     torch.cuda.synchronize()
     t = hev.ms(0, 1) / args.steps
     hev.close()
@@ -557,244 +1002,36 @@ def bench_copy(args, n, dev):
                                                       "bytes_per_launch": 8 * n}}), flush=True)
 
 
-def bench_range(args, n, m, seed, dev):
-    import numpy as np
-    import torch
-
-    from paper_1701_01189_amd import binding as ms
-    from paper_1701_01189_amd import inputs
-    keys = inputs.lognormal_u32(seed, n)
-    spl = inputs.quantile_splitters(inputs.lognormal_u32(1031, 1 << 16), m)
-    fit = inputs.lognormal_u32(1032, 1 << 20)
-    dk = torch.from_numpy(keys.view(np.int32)).to(dev)
-    ds = torch.from_numpy(spl.view(np.int32)).to(dev)
-    dfit = torch.from_numpy(fit.view(np.int32)).to(dev)
-    torch.cuda.synchronize()
-    f0 = time.perf_counter()
-    model = ms.learned_fit(dfit, ds, m)
-    torch.cuda.synchronize()
-    fit_ms = (time.perf_counter() - f0) * 1e3
-    ok = torch.empty_like(dk)
-    off = torch.empty(m + 1, dtype=torch.int32, device=dev)
-    base = dict(reorder=args.reorder, waves_per_block=args.waves, items_per_lane=args.items,
-                max_chunks=args.chunks)
-    ws = torch.empty(max(256, ms.workspace_size(ms.OP_KEYS, n, m, 0, ms.Options(**base))),
-                     dtype=torch.uint8, device=dev)
-    res = {}
-    for name, fn in (("learned", ms.BucketFn.learned(ds, model)),
-                     ("binary_search", ms.BucketFn.splitter(ds))):
-        def step(ev, fn=fn):
-            ms.keys(dk, m, fn, keys_out=ok, offsets=off, options=ms.Options(stage_events=ev, **base),
-                    ws=ws)
-        res[name] = time_steps(step, args.steps, args.warmup)
-    miss = torch.zeros(1, dtype=torch.int64, device=dev)
-    ms.keys(dk, m, ms.BucketFn.learned(ds, model), keys_out=ok, offsets=off,
-            options=ms.Options(mispredicts=miss, **base), ws=ws)
-    torch.cuda.synchronize()
-    lt, lst = res["learned"]
-    bt, bst = res["binary_search"]
-    value = n / (lt * 1e-3) / 1e9
-    post_gbps = n * 8 / (lst[2] * 1e-3) / 1e9
-    line = {
-        "metric": METRIC, "value": round(value, 3), "unit": "Gkeys/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(lt, 5),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
-        "data": "synthetic",
-        "config": {"workload": args.workload, "n": n, "m": m, "bucket": "learned range",
-                   "keys": "lognormal(20,2) saturated", "seed": seed, **base},
-        "stage_ms": {"prescan": round(lst[0], 5), "scan": round(lst[1], 5),
-                     "postscan": round(lst[2], 5)},
-        "binary_search": {"value": round(n / (bt * 1e-3) / 1e9, 3), "ms_per_step": round(bt, 5),
-                          "stage_ms": {"prescan": round(bst[0], 5), "scan": round(bst[1], 5),
-                                       "postscan": round(bst[2], 5)}},
-        "learned_speedup": round(bt / lt, 4),
-        "mispredict_rate": round(int(miss.item()) / n, 5),
-        "fit_ms_wall": round(fit_ms, 3),
-        "roofline": {"bound": "hbm", "kernel": "postscan", "achieved": round(post_gbps, 1),
-                     "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": round(post_gbps / HBM_PEAK_GBPS, 4),
-                     "traffic": traffic_for("postscan", args.workload, n), "bytes_per_unit": 8},
-    }
-    if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline("range", keys, spl, m, 0, args.cpu_seconds)
-    print(json.dumps(line), flush=True)
-
-
 def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py: the multisplit library runs on one GPU; only --gpus 1 is "
               "measured (--gpus %d is not supported)" % args.gpus, file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
 
-    from paper_1701_01189_amd import binding as ms
     from paper_1701_01189_amd import build as b
-    from paper_1701_01189_amd import inputs
 
     if not os.path.exists(b.LIB):
         b.build(force=True)
-    kind, n, m, shift, seed = workload(args.workload)
-    kv = kind.startswith("pairs") or kind == "radix_pairs"
     dev = torch.device("cuda:0")
-    if kind == "range":
-        return bench_range(args, n, m, seed, dev)
-    if kind == "copy":
-        return bench_copy(args, n, dev)
-    if kind == "batched":
-        return bench_batched(args, n, m, shift, seed, dev)
-    if kind == "sssp":
-        return bench_sssp(args, n, m, shift, seed, dev)
-    if kind in ("hist", "histrange"):
-        return bench_hist(args, kind, n, m, shift, seed, dev)
-    ident = kind.endswith("_ident")
-    if ident:
-        kind = kind[:-len("_ident")]
-    keys = inputs.uniform_u32(seed, n)
-    if ident:
-        keys &= np.uint32(m - 1)
-    vals = inputs.index_values(n) if kv else None
-    dk = torch.from_numpy(keys.view(np.int32)).to(dev)
-    dv = torch.from_numpy(vals.view(np.int32)).to(dev) if kv else None
-    ok = torch.empty_like(dk)
-    ov = torch.empty_like(dv) if kv else None
-    off = torch.empty(m + 1, dtype=torch.int32, device=dev)
-    opt = ms.Options(reorder=args.reorder, waves_per_block=args.waves,
-                     items_per_lane=args.items, max_chunks=args.chunks)
-    radix = kind.startswith("radix")
-    op = (ms.OP_RADIX_SORT_PAIRS if kv else ms.OP_RADIX_SORT) if radix else \
-        (ms.OP_PAIRS if kv else ms.OP_KEYS)
-    ws = torch.empty(max(256, ms.workspace_size(op, n, m, 0, opt)), dtype=torch.uint8,
-                     device=dev)
-    # powers of two: shift/mask; other m: delta buckets floor(k / ceil(2^32 / m))
-    pow2 = m & (m - 1) == 0
-    fn = ms.BucketFn.shift_mask(shift, m - 1) if pow2 else ms.BucketFn.div(-(-(1 << 32) // m))
-
-    def step(o):
-        if radix:
-            ms.radix_sort(dk, dv, shift, keys_out=ok, vals_out=ov, options=o, ws=ws)
-        elif kv:
-            ms.pairs(dk, dv, m, fn, keys_out=ok, vals_out=ov, offsets=off, options=o, ws=ws)
-        else:
-            ms.keys(dk, m, fn, keys_out=ok, offsets=off, options=o, ws=ws)
-
-    for _ in range(args.warmup):
-        step(opt)
-    K = args.steps
-    hev = HipEvents(4 * K)
-    evs = [[_Handle(hev.ev[4 * i + j]) for j in range(4)] for i in range(K)]
-    cev = HipEvents(K + 1)  # call boundaries (a radix sort records stages of its last pass only)
-    stream = torch.cuda.current_stream()
-    torch.cuda.synchronize()
-    t_start = torch.cuda.Event(enable_timing=True)
-    t_end = torch.cuda.Event(enable_timing=True)
-    w0 = time.perf_counter()
-    t_start.record(stream)
-    for i in range(K):
-        o = ms.Options(reorder=args.reorder, waves_per_block=args.waves,
-                       items_per_lane=args.items, max_chunks=args.chunks, stage_events=evs[i])
-        cev.record(i)
-        step(o)
-    cev.record(K)
-    t_end.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    total_ms = t_start.elapsed_time(t_end)
-    ms_per_step = total_ms / K
-    stage = [0.0, 0.0, 0.0]
-    for i in range(K):
-        for s in range(3):
-            stage[s] += hev.ms(4 * i + s, 4 * i + s + 1) / K
-    per_call = [cev.ms(i, i + 1) for i in range(K)]
-    hev.close()
-    cev.close()
-    cold = None
-    if args.cold_reps > 0:
-        cold = summary(cold_steps(lambda _ev: step(opt), args.cold_reps, dev), n)
-    # The same call captured in a HIP graph and replayed K times: the GPU's
-    # own time per call, without the host's cost of issuing it from Python.
-    # For small inputs (2^20 keys: ~25 us of GPU work) the eager loop measures
-    # the host, so `value` is taken from the replays there.
-    side = torch.cuda.Stream()
-    side.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(side):
-        step(opt)
-    torch.cuda.current_stream().wait_stream(side)
-    torch.cuda.synchronize()
-    graph = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(graph):
-        step(opt)
-    for _ in range(args.warmup):
-        graph.replay()
-    torch.cuda.synchronize()
-    g0 = torch.cuda.Event(enable_timing=True)
-    g1 = torch.cuda.Event(enable_timing=True)
-    g0.record()
-    for _ in range(K):
-        graph.replay()
-    g1.record()
-    torch.cuda.synchronize()
-    graph_ms = g0.elapsed_time(g1) / K
-    del graph
-    ceiling = None if args.no_ceiling else copy_ceiling(dev)
-    # correctness spot check of the last step against the properties of the
-    # unique stable result is done by the tests; here only a cheap sanity check
-    units = n
-    small = n <= (1 << 22)
-    timed_ms = graph_ms if small else ms_per_step
-    value = units / (timed_ms * 1e-3) / 1e9
-    # dominant kernel: the post-scan (of the last pass for the radix sort)
-    post_bytes = n * (16 if kv else 8)
-    post_ms = stage[2]
-    achieved = post_bytes / (post_ms * 1e-3) / 1e9
-    traffic = traffic_for("postscan", args.workload, n)
-    line = {
-        "metric": METRIC,
-        "value": round(value, 3),
-        "unit": "Gpairs/s" if kv else "Gkeys/s",
-        "n_gpus": 1,
-        "steps": K,
-        "warmup": args.warmup,
-        "ms_per_step": round(timed_ms, 5),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u32",
-        "data": "synthetic",
-        "timing": "hipgraph replays" if small else "eager calls",
-        "eager_value": round(units / (ms_per_step * 1e-3) / 1e9, 3),
-        "graph_value": round(units / (graph_ms * 1e-3) / 1e9, 3),
-        "config": {"workload": args.workload, "n": n, "m": m,
-                   "bucket": ("radix %d x %d-bit digits" % (-(-32 // shift), shift) if radix else
-                              "identity (keys < m)" if ident else
-                              "shift_mask" if pow2 else "delta ceil(2^32/m)"),
-                   "shift": shift, "kv": kv, "seed": seed,
-                   "reorder": args.reorder, "waves_per_block": args.waves,
-                   "items_per_lane": args.items},
-        "stage_ms": {"prescan": round(stage[0], 5), "scan": round(stage[1], 5),
-                     "postscan": round(stage[2], 5)},
-        "wall_s": round(wall, 4),
-        "roofline": {"bound": "hbm", "kernel": "postscan", "achieved": round(achieved, 1),
-                     "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                     "traffic": traffic,
-                     "bytes_per_unit": 16 if kv else 8,
-                     "whole_call_algorithmic_GBps": round(n * (20 if kv else 12) /
-                                                          (timed_ms * 1e-3) / 1e9, 1)},
-        "warm_per_call": summary(per_call, n),
-    }
-    if cold is not None:
-        line["cold_per_call"] = cold
-    if ceiling is not None:
-        line["roofline"]["copy_ceiling_GBps"] = round(ceiling, 1)
-        line["roofline"]["frac_of_copy_ceiling"] = round(achieved / ceiling, 4)
-    if radix:
-        line["roofline"]["whole_call_algorithmic_GBps"] = round(
-            n * -(-32 // shift) * (20 if kv else 12) / (timed_ms * 1e-3) / 1e9, 1)
-    if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(kind, keys, vals, m, shift, args.cpu_seconds)
-    print(json.dumps(line), flush=True)
+    w = args.workload
+    if w == "headline":
+        return headline(args, dev)
+    if w == "range_2e27_m256":
+        return single_line(args, row_config3(args, dev, None))
+    if w == "batched_4096_m64":
+        return single_line(args, row_config4(args, dev))
+    if w == "copy_2e28":
+        return bench_copy(args, 1 << 28, dev)
+    if w.startswith("sssp_rmat_2e20"):
+        delta = int(w.split("_d")[1]) if "_d" in w else 800
+        return bench_sssp(args, 20, 4_800_000, delta, 106, dev)
+    if w.startswith("hist_") or w.startswith("histrange_"):
+        size, mm = w.split("_")[1], int(w.split("_m")[1])
+        return bench_hist(args, w.split("_")[0], 1 << int(size[2:]), mm,
+                          32 - (mm - 1).bit_length(), 110, dev)
+    return single_multisplit(args, w, dev)
 
 
 if __name__ == "__main__":

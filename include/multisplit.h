@@ -137,6 +137,8 @@ enum {
  *                    instance's ready flag before giving up (0 = 2^22).
  *   test_flags       bit 0: ms_batched never raises ready flags, so every
  *                    wait expires (exercises the timeout path; for tests).
+ *                    bit 1: ms_autotune treats its first candidate as
+ *                    failed (exercises the skip of failing candidates).
  *   prescan          MS_PRESCAN_*: how the pre-scan counts buckets.
  */
 typedef struct {
@@ -223,9 +225,11 @@ ms_status ms_pairs(const uint32_t* d_keys_in, const uint32_t* d_vals_in,
 
 /*
  * Device-wide histogram (Section 7.3): d_hist[j] = number of the n keys with
- * fn(key) = j, for j < m.  It is the multisplit pre-scan with every
- * subproblem's counts added into d_hist by atomics; no key moves.  Even bins
- * are SHIFT_MASK or DIV buckets, range bins SPLITTERS or LEARNED buckets.
+ * fn(key) = j, for j < m.  It is the multisplit pre-scan (one count per
+ * bucket and subproblem), followed by a per-bucket reduction of those counts
+ * into d_hist (Section 7.3's store-and-reduce option); no key moves.  Even
+ * bins are SHIFT_MASK or DIV buckets, range bins SPLITTERS or LEARNED
+ * buckets.
  *   d_keys   n uint32 keys (device).  n = 0 writes m zeros.
  *   d_hist   m uint32 (device), overwritten; must not overlap d_keys.
  *   d_ws     ms_workspace_size(MS_OP_HISTOGRAM, n, m, 0, opt) bytes.
@@ -276,18 +280,29 @@ ms_status ms_batched(const uint32_t* d_keys_in, const uint32_t* d_vals_in,
 ms_status ms_batched_status(const void* d_ws, void* stream);
 
 /*
- * Fit the learned bucket model for range buckets given by m-1 ascending
- * device splitters, from n_sample device sample keys.  Labels are the exact
- * upper bounds.  Root: least squares of y*256/m on x = (float)key.  Every
- * sample is routed to a leaf by the root evaluated in float; each leaf is a
- * least-squares line of y on x; an empty leaf copies its nearest non-empty
- * left neighbour (else right).  Sums are in double, in a fixed order, so the
- * result is deterministic.  d_model receives MS_MODEL_FLOATS floats.
+ * Fit the learned bucket model for range buckets from n_sample device sample
+ * keys (not in the paper; Section 7.3 finds range buckets by binary search).
+ *   d_sample     n_sample uint32 keys, 1 <= n_sample < 2^32 - 1.
+ *   d_labels     n_sample uint32 bucket ids, or NULL: the labels are then
+ *                the exact upper bounds over the splitters (the ids that
+ *                MS_BUCKET_SPLITTERS gives).  Given labels at or above m
+ *                count as m - 1.
+ *   d_splitters  m-1 ascending uint32 (may be NULL when d_labels is given).
+ *   d_model      receives MS_MODEL_FLOATS floats.
+ * Root: the line that maps the sample's key range [x_min, x_max], x =
+ * (float)key, onto the leaves [0, 256): x_min to 0, x_max to 256 (clamped to
+ * 255 when evaluated).  Each sample is routed to a leaf by that root
+ * evaluated in float exactly as at inference.  Each leaf is the
+ * least-squares line of the bucket centre (label + 1/2) on x over its
+ * samples; a leaf with no samples copies its nearest non-empty neighbour
+ * (left first, else right).  The sums are exact integers, so the fit is
+ * deterministic.  Workspace: ms_workspace_size(MS_OP_LEARNED_FIT, n_sample,
+ * m, 0, NULL) bytes (a few KiB, independent of n_sample).
  */
-ms_status ms_learned_fit(const uint32_t* d_sample, size_t n_sample,
-                         const uint32_t* d_splitters, uint32_t m,
-                         float* d_model, void* d_ws, size_t ws_bytes,
-                         void* stream);
+ms_status ms_learned_fit(const uint32_t* d_sample, const uint32_t* d_labels,
+                         size_t n_sample, const uint32_t* d_splitters,
+                         uint32_t m, float* d_model, void* d_ws,
+                         size_t ws_bytes, void* stream);
 
 /*
  * Autotuner: runs `op` (MS_OP_KEYS, MS_OP_PAIRS, MS_OP_BATCHED,
@@ -297,8 +312,9 @@ ms_status ms_learned_fit(const uint32_t* d_sample, size_t n_sample,
  * times each after one warm-up, and writes the fastest candidate to *best
  * (fields other than the tuned ones are copied from `base`, which may be
  * NULL) and its mean time in milliseconds to *best_ms.  The outputs hold the
- * result of the last run.  Candidates whose workspace exceeds ws_bytes are
- * skipped.  Arguments as for the operation itself (d_seg / num_inst for
+ * result of a final run with the winner.  Candidates whose workspace exceeds
+ * ws_bytes, and candidates whose run fails, are skipped; the call returns
+ * the last failure only if no candidate ran.  Arguments as for the operation itself (d_seg / num_inst for
  * MS_OP_BATCHED only, fn ignored for the radix sort, m = bits per pass for
  * the radix sort).  Synchronises `stream`; not capture-safe.
  */

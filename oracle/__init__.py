@@ -70,7 +70,7 @@ def _load():
     lib.or_learned_leaf.restype = u32
     lib.or_learned_predict.argtypes = [PF, u32, u32]
     lib.or_learned_predict.restype = u32
-    lib.or_learned_fit.argtypes = [P32, u64, P32, u32, PF]
+    lib.or_learned_fit.argtypes = [P32, u64, P32, u32, P32, PF]
     lib.or_learned_fit.restype = None
     lib.or_learned_bucket_ids.argtypes = [PF, P32, u32, P32, u64, P32, P64]
     lib.or_learned_bucket_ids.restype = None
@@ -164,11 +164,14 @@ def _fp(model):
     return model.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
 
 
-def learned_fit(sample, splitters, m):
+def learned_fit(sample, splitters, m, labels=None):
+    """The model fitted to sample keys labelled by the upper bound over the
+    splitters, or by `labels` (clamped to m - 1) when given."""
     sample = _c32(sample)
     spl = _c32(splitters)
+    lab = _c32(labels) if labels is not None else None
     model = np.zeros(2 + 2 * LEAVES, dtype=np.float32)
-    _load().or_learned_fit(_u32p(sample), len(sample), _u32p(spl), m, _fp(model))
+    _load().or_learned_fit(_u32p(sample), len(sample), _u32p(spl), m, _u32p(lab), _fp(model))
     return model
 
 

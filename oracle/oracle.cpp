@@ -215,7 +215,8 @@ static void lsq_line(const std::vector<double>& x, const std::vector<double>& y,
   *ok = 1;
 }
 
-// Fit the two-stage model to sample keys labelled by the exact upper bound.
+// Fit the two-stage model to sample keys labelled by the exact upper bound
+// (or by the given labels, clamped to m - 1, when labels is not null).
 // Root: the line that maps the sample's key range [x_min, x_max] onto the
 // leaves [0, L) (x_min to 0, x_max to L, clamped to L-1), so that every leaf
 // covers an equal slice of the key range.  Leaves: least squares of the
@@ -223,12 +224,14 @@ static void lsq_line(const std::vector<double>& x, const std::vector<double>& y,
 // so truncation of the line lands inside the bucket.  An empty leaf copies
 // the nearest non-empty leaf to its left (else to its right).
 void or_learned_fit(const uint32_t* sample, uint64_t ns, const uint32_t* spl,
-                    uint32_t m, float* model) {
+                    uint32_t m, const uint32_t* labels, float* model) {
   std::vector<double> x(ns), y(ns);
   double xmin = 0, xmax = 0;
   for (uint64_t i = 0; i < ns; ++i) {
     x[i] = (double)(float)sample[i];
-    y[i] = (double)upper_bound_count(spl, m - 1, sample[i]) + 0.5;
+    const uint32_t lab = labels ? (labels[i] < m ? labels[i] : m - 1)
+                                : upper_bound_count(spl, m - 1, sample[i]);
+    y[i] = (double)lab + 0.5;
     if (i == 0 || x[i] < xmin) xmin = x[i];
     if (i == 0 || x[i] > xmax) xmax = x[i];
   }

@@ -94,7 +94,7 @@ def lib():
     L.ms_autotune.restype = i32
     L.ms_batched_status.argtypes = [vp, vp]
     L.ms_batched_status.restype = i32
-    L.ms_learned_fit.argtypes = [vp, sz, vp, u32, vp, vp, sz, vp]
+    L.ms_learned_fit.argtypes = [vp, vp, sz, vp, u32, vp, vp, sz, vp]
     L.ms_learned_fit.restype = i32
     L.ms_copy_u32.argtypes = [vp, vp, sz, vp]
     L.ms_copy_u32.restype = i32
@@ -357,18 +357,22 @@ def batched_status(ws, stream=None):
     return int(lib().ms_batched_status(_ptr(ws), _stream(stream)))
 
 
-def learned_fit(sample, splitters, m, model=None, stream=None, ws=None):
-    """Fits the two-stage learned bucket model on the GPU.  Returns the model
+def learned_fit(sample, splitters, m, model=None, labels=None, stream=None, ws=None):
+    """Fits the two-stage learned bucket model on the GPU, to the upper-bound
+    bucket ids over the splitters or to the given labels.  Returns the model
     tensor (MODEL_FLOATS float32)."""
     import torch
     if model is None:
         model = torch.empty(MODEL_FLOATS, dtype=torch.float32, device=sample.device)
     n = sample.numel()
+    if labels is not None and labels.numel() != n:
+        raise ValueError("labels and sample differ in length")
     if ws is None:
         need = workspace_size(OP_LEARNED_FIT, n, m)
         ws = torch.empty(max(need, 256), dtype=torch.uint8, device=sample.device)
-    rc = lib().ms_learned_fit(_u32(sample, "sample"), n, _u32(splitters, "splitters"), m,
-                              _ptr(model), _ptr(ws), ws.numel(), _stream(stream))
+    rc = lib().ms_learned_fit(_u32(sample, "sample"), _u32(labels, "labels"), n,
+                              _u32(splitters, "splitters"), m, _ptr(model), _ptr(ws),
+                              ws.numel(), _stream(stream))
     _check(rc, "ms_learned_fit")
     return model
 

@@ -36,9 +36,9 @@ __device__ __forceinline__ uint32_t lane_id() {
   return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
 }
 
-// Number of set bits of `mask` at lanes strictly below this lane.  This is
-// the "mask away higher lanes, then population count" step of Algorithm 3,
-// done by the hardware's masked bit count.
+// Number of set bits of `mask` at lanes strictly below this lane: Algorithm
+// 3's count of same-bucket lanes below this one, done by the hardware's
+// masked bit count.
 __device__ __forceinline__ uint32_t count_below(uint64_t mask) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                    __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));

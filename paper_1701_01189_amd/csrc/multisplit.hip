@@ -519,9 +519,10 @@ size_t ms_workspace_size(int op, size_t n, uint32_t m, uint32_t num_inst, const 
       return batch_layout(n, m, num_inst, bs, nullptr, nullptr);
     }
     case MS_OP_LEARNED_FIT: {
+      // per-workgroup key ranges, then the per-leaf integer sums
       if (n == 0 || n >= 0xFFFFFFFFull) return 0;
-      return align_up(2 * ms::kFitBlocks * sizeof(double), kWsAlign) +
-             align_up((8 + ms::kLeaves) * sizeof(double), kWsAlign) + 2 * align_up(n * 4, kWsAlign);
+      return align_up(2 * ms::kFitBlocks * sizeof(uint32_t), kWsAlign) +
+             align_up((size_t)ms::kLeaves * ms::kFitAccWords * 8, kWsAlign);
     }
     default:
       return 0;
@@ -717,34 +718,33 @@ ms_status ms_batched_status(const void* d_ws, void* stream) {
   return ctl[1] ? MS_ERR_TIMEOUT : MS_OK;
 }
 
-ms_status ms_learned_fit(const uint32_t* d_sample, size_t n_sample, const uint32_t* d_splitters,
-                         uint32_t m, float* d_model, void* d_ws, size_t ws_bytes, void* stream) {
+ms_status ms_learned_fit(const uint32_t* d_sample, const uint32_t* d_labels, size_t n_sample,
+                         const uint32_t* d_splitters, uint32_t m, float* d_model, void* d_ws,
+                         size_t ws_bytes, void* stream) {
   if (m < 1 || m > (uint32_t)ms::kMaxBuckets) return MS_ERR_INVALID_ARG;
   if (n_sample == 0 || n_sample >= 0xFFFFFFFFull) return MS_ERR_INVALID_ARG;
-  if (!d_sample || !d_model || (m > 1 && !d_splitters)) return MS_ERR_INVALID_ARG;
+  if (!d_sample || !d_model || (m > 1 && !d_splitters && !d_labels)) return MS_ERR_INVALID_ARG;
   size_t need = ms_workspace_size(MS_OP_LEARNED_FIT, n_sample, m, 0, nullptr);
   if (!d_ws || ws_bytes < need) return MS_ERR_WORKSPACE;
   hipStream_t st = (hipStream_t)stream;
   char* b = (char*)d_ws;
   ms::FitParams p;
   p.sample = d_sample;
+  p.labels = d_labels;
   p.ns = (uint32_t)n_sample;
-  p.splitters = d_splitters;
+  p.splitters = m > 1 ? d_splitters : nullptr;
   p.m = m;
   p.model = d_model;
-  p.partial = (double*)b;
-  b += align_up(2 * ms::kFitBlocks * sizeof(double), kWsAlign);
-  p.moments = (double*)b;
-  b += align_up((8 + ms::kLeaves) * sizeof(double), kWsAlign);
-  p.labels = (uint32_t*)b;
-  b += align_up(n_sample * 4, kWsAlign);
-  p.leaves = (uint32_t*)b;
-  dim3 G(ms::kFitBlocks), B(ms::kFitThreads);
-  hipLaunchKernelGGL(ms::fit_label_kernel, G, B, 0, st, p);
+  p.range = (uint32_t*)b;
+  b += align_up(2 * ms::kFitBlocks * sizeof(uint32_t), kWsAlign);
+  p.acc = (unsigned long long*)b;
+  dim3 B(ms::kFitThreads);
+  hipLaunchKernelGGL(ms::fit_range_kernel, dim3(ms::kFitBlocks), B, 0, st, p);
   hipLaunchKernelGGL(ms::fit_root_kernel, dim3(1), B, 0, st, p);
-  hipLaunchKernelGGL(ms::fit_route_kernel, G, B, 0, st, p);
-  hipLaunchKernelGGL(ms::fit_leaf_kernel, dim3(ms::kLeaves), B, 0, st, p);
-  hipLaunchKernelGGL(ms::fit_fill_empty_kernel, dim3(1), dim3(64), 0, st, p);
+  hipLaunchKernelGGL(ms::fit_sum_kernel<1>, dim3(ms::kFitSumBlocks), B, 0, st, p);
+  hipLaunchKernelGGL(ms::fit_mean_kernel, dim3(1), B, 0, st, p);
+  hipLaunchKernelGGL(ms::fit_sum_kernel<2>, dim3(ms::kFitSumBlocks), B, 0, st, p);
+  hipLaunchKernelGGL(ms::fit_finish_kernel, dim3(1), B, 0, st, p);
   return hipGetLastError() == hipSuccess ? MS_OK : MS_ERR_HIP;
 }
 
@@ -776,7 +776,11 @@ ms_status ms_autotune(int op, const uint32_t* d_keys_in, const uint32_t* d_vals_
     (void)hipEventDestroy(e0);
     return MS_ERR_HIP;
   }
-  ms_status result = MS_ERR_UNSUPPORTED;
+  // A candidate that fails (an unsupported shape, a launch error) is skipped
+  // and the search goes on; the call fails only when every candidate did,
+  // with the last candidate's error.
+  ms_status last_err = MS_ERR_UNSUPPORTED;
+  bool have = false;
   float best_t = 0.0f;
   for (int c = 0; c < ncand; ++c) {
     ms_options o;
@@ -788,6 +792,11 @@ ms_status ms_autotune(int op, const uint32_t* d_keys_in, const uint32_t* d_vals_
     o.items_per_lane = cands[c].nw;
     if (batched) o.batch_claim = cands[c].claim;
     if (o.prescan == MS_PRESCAN_LANES && o.reorder != MS_REORDER_BLOCK) o.prescan = MS_PRESCAN_AUTO;
+    if (c == 0 && base && (base->test_flags & 2u)) {  // test hook: the first candidate fails
+      last_err = MS_ERR_UNSUPPORTED;
+      continue;
+    }
+    o.test_flags &= ~2u;
     int wop = batched ? MS_OP_BATCHED
                       : radix ? (d_vals_in ? MS_OP_RADIX_SORT_PAIRS : MS_OP_RADIX_SORT)
                               : (d_vals_in ? MS_OP_PAIRS : MS_OP_KEYS);
@@ -803,37 +812,53 @@ ms_status ms_autotune(int op, const uint32_t* d_keys_in, const uint32_t* d_vals_
       return ms_pairs(d_keys_in, d_vals_in, d_keys_out, d_vals_out, nullptr, n, m, fn, d_ws,
                       ws_bytes, &o, stream);
     };
-    ms_status rc = run();
+    ms_status rc = run();  // warm-up
     if (rc != MS_OK) {
-      result = rc;
-      break;
+      last_err = rc;
+      continue;
     }
     if (hipEventRecord(e0, st) != hipSuccess) {
-      result = MS_ERR_HIP;
+      last_err = MS_ERR_HIP;
       break;
     }
     for (int r = 0; r < reps && rc == MS_OK; ++r) rc = run();
-    if (rc != MS_OK || hipEventRecord(e1, st) != hipSuccess ||
-        hipEventSynchronize(e1) != hipSuccess) {
-      result = rc != MS_OK ? rc : MS_ERR_HIP;
+    if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+      last_err = MS_ERR_HIP;
       break;
+    }
+    if (rc != MS_OK) {
+      last_err = rc;
+      continue;
     }
     float t = 0.0f;
     if (hipEventElapsedTime(&t, e0, e1) != hipSuccess) {
-      result = MS_ERR_HIP;
+      last_err = MS_ERR_HIP;
       break;
     }
     t /= (float)reps;
-    if (result != MS_OK || t < best_t) {
+    if (!have || t < best_t) {
       best_t = t;
       *best = o;
-      result = MS_OK;
+      have = true;
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  if (result == MS_OK && best_ms) *best_ms = best_t;
-  return result;
+  if (have && best_ms) *best_ms = best_t;
+  // With a winner, the outputs are rewritten with it, so that they hold its
+  // result whatever candidate ran last.
+  if (have) {
+    ms_options o = *best;
+    if (batched)
+      return ms_batched(d_keys_in, d_vals_in, d_keys_out, d_vals_out, d_seg, num_inst, n, m, fn,
+                        nullptr, d_ws, ws_bytes, &o, stream);
+    if (radix)
+      return ms_radix_sort(d_keys_in, d_vals_in, d_keys_out, d_vals_out, n, m, d_ws, ws_bytes,
+                           &o, stream);
+    return ms_pairs(d_keys_in, d_vals_in, d_keys_out, d_vals_out, nullptr, n, m, fn, d_ws,
+                    ws_bytes, &o, stream);
+  }
+  return last_err;
 }
 
 ms_status ms_copy_u32(uint32_t* d_dst, const uint32_t* d_src, size_t n, void* stream) {

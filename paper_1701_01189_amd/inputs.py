@@ -19,6 +19,9 @@ workloads that stand beside the plain method.
 """
 from __future__ import annotations
 
+import os
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
 
 GAMMA = np.uint64(0x9E3779B97F4A7C15)
@@ -52,12 +55,30 @@ def splitmix64(seed: int, count: int, start: int = 0) -> np.ndarray:
     return out
 
 
+def _threads() -> int:
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def _chunked(n: int, fill) -> None:
+    """Calls fill(lo, hi) over chunks of [0, n), in parallel threads when n is
+    large (numpy releases the interpreter lock inside its array loops).  The
+    draws are counter based, so the result does not depend on the split."""
+    spans = [(lo, min(n, lo + _CHUNK)) for lo in range(0, n, _CHUNK)]
+    if len(spans) <= 1:
+        for lo, hi in spans:
+            fill(lo, hi)
+        return
+    with ThreadPoolExecutor(_threads()) as ex:
+        list(ex.map(lambda sp: fill(*sp), spans))
+
+
 def uniform_u32(seed: int, n: int) -> np.ndarray:
     """n uint32 keys uniform over [0, 2^32)."""
     out = np.empty(n, dtype=np.uint32)
-    for lo in range(0, n, _CHUNK):
-        hi = min(n, lo + _CHUNK)
+
+    def fill(lo, hi):
         out[lo:hi] = (splitmix64(seed, hi - lo, lo) >> np.uint64(32)).astype(np.uint32)
+    _chunked(n, fill)
     return out
 
 
@@ -77,14 +98,15 @@ def lognormal_u32(seed: int, n: int, mu: float = 20.0, sigma: float = 2.0) -> np
     z comes from Box-Muller on draws 2i and 2i+1: z = sqrt(-2 ln(1-u1)) cos(2 pi u2).
     """
     out = np.empty(n, dtype=np.uint32)
-    for lo in range(0, n, _CHUNK):
-        hi = min(n, lo + _CHUNK)
+
+    def fill(lo, hi):
         u = uniform_f64(seed, 2 * (hi - lo), 2 * lo)
         u1, u2 = u[0::2], u[1::2]
         z = np.sqrt(-2.0 * np.log1p(-u1)) * np.cos(2.0 * np.pi * u2)
         v = np.floor(np.exp(mu + sigma * z))
         v = np.minimum(v, 4294967295.0)
         out[lo:hi] = v.astype(np.uint32)
+    _chunked(n, fill)
     return out
 
 
@@ -103,8 +125,11 @@ def skewed_bucket_keys(seed: int, n: int, m: int, dist: str, alpha: float = 0.25
     """Keys whose delta bucket k >> (32 - log2 m) follows a chosen distribution.
 
     dist = "uniform":   bucket uniform over [0, m)
-    dist = "binomial":  bucket ~ B(m-1, p) (Section 6.4), drawn as a sum of
-                        m-1 Bernoulli(p) trials
+    dist = "binomial":  bucket ~ B(m-1, p) (Section 6.4): for p = 1/2 the
+                        number of set bits among m-1 uniform random bits
+                        (ceil((m-1)/64) draws per key, draw W*i + w for
+                        word w of key i, bits above m-1 cleared), otherwise
+                        a sum of m-1 Bernoulli(p) trials
     dist = "alpha":     with probability alpha the bucket is uniform, else it
                         is one fixed bucket drawn from the seed (alpha-uniform)
     The low bits inside the bucket are uniform.  m must be a power of two.
@@ -116,6 +141,19 @@ def skewed_bucket_keys(seed: int, n: int, m: int, dist: str, alpha: float = 0.25
     low = low & np.uint32((1 << shift) - 1) if shift < 32 else low
     if dist == "uniform":
         b = (uniform_u32(seed, n).astype(np.uint64) * np.uint64(m)) >> np.uint64(32)
+    elif dist == "binomial" and p == 0.5:
+        trials = m - 1
+        words = max(1, -(-trials // 64))
+        top = trials - 64 * (words - 1)
+        top_mask = np.uint64((1 << top) - 1) if top < 64 else np.uint64(0xFFFFFFFFFFFFFFFF)
+        b = np.zeros(n, dtype=np.int64)
+
+        def fill(lo, hi):
+            w = splitmix64(seed + 7919, words * (hi - lo), words * lo).reshape(hi - lo, words)
+            w[:, words - 1] &= top_mask
+            b[lo:hi] = np.bitwise_count(w).sum(axis=1, dtype=np.int64)
+        if trials > 0:
+            _chunked(n, fill)
     elif dist == "binomial":
         b = np.zeros(n, dtype=np.int64)
         trials = m - 1
@@ -154,12 +192,14 @@ def batched_pairs(seed: int, sizes: np.ndarray):
     total = int(np.sum(sizes))
     keys = np.empty(total, dtype=np.uint32)
     vals = np.empty(total, dtype=np.uint32)
-    pos = 0
-    for i, s in enumerate(sizes):
-        s = int(s)
+    starts = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+
+    def fill(i):
+        pos, s = int(starts[i]), int(sizes[i])
         keys[pos:pos + s] = uniform_u32(seed * 1000 + i, s)
         vals[pos:pos + s] = np.arange(s, dtype=np.uint32)
-        pos += s
+    with ThreadPoolExecutor(_threads()) as ex:
+        list(ex.map(fill, range(len(sizes))))
     return keys, vals
 
 

@@ -142,3 +142,41 @@ def test_tuned_options_measures_once_then_reads_the_cache(tmp_path):
     k, o = ms.keys(dk, 16, fn, options=opt2)
     np.testing.assert_array_equal(host(k), ek)
     np.testing.assert_array_equal(host(o), eo)
+
+
+@pytest.mark.parametrize("op", ["keys", "batched"])
+def test_autotune_skips_a_failing_candidate(op):
+    """With test flag bit 1 the first candidate reports failure: the search
+    goes on, the winner is another candidate and the operation run with it
+    is still exact."""
+    from paper_1701_01189_amd import binding as ms
+    m = 32
+    fn = ms.BucketFn.shift_mask(27, 31)
+    base = ms.Options(test_flags=2)
+    if op == "keys":
+        n = (1 << 20) + 3
+        keys = inputs.uniform_u32(61, n)
+        dk = dev(keys)
+        say("case autotune failing first candidate keys")
+        opt, t = ms.autotune(ms.OP_KEYS, dk, None, m, fn=fn, reps=1, base=base)
+        assert (opt.reorder, opt.waves_per_block, opt.items_per_lane) in MULTI - {(1, 8, 8)}
+        assert opt.test_flags == 0 and t > 0.0
+        k, o = ms.keys(dk, m, fn, options=opt)
+        ek, _, eo = oracle.multisplit(keys, m, oracle.SHIFT_MASK, shift=27, mask=31)
+        np.testing.assert_array_equal(host(k), ek)
+        np.testing.assert_array_equal(host(o), eo)
+    else:
+        sizes = inputs.batched_sizes(62, 40)
+        seg = inputs.segment_offsets(sizes)
+        keys, vals = inputs.batched_pairs(62, sizes)
+        dk, dv = dev(keys), dev(vals)
+        ds = torch.from_numpy(seg.astype(np.int64)).cuda()
+        say("case autotune failing first candidate batched")
+        opt, t = ms.autotune(ms.OP_BATCHED, dk, dv, m, fn=fn, seg=ds, reps=1, base=base)
+        assert (opt.waves_per_block, opt.items_per_lane, opt.batch_claim) in BATCH - {(8, 8, 1)}
+        assert opt.test_flags == 0
+        k, v, o, _ = ms.batched(dk, dv, ds, m, fn, options=opt)
+        ek, ev, eo = oracle.batched(keys, vals, seg, m, oracle.SHIFT_MASK, shift=27, mask=31)
+        np.testing.assert_array_equal(host(k), ek)
+        np.testing.assert_array_equal(host(v), ev)
+        np.testing.assert_array_equal(host(o), eo)

@@ -93,13 +93,28 @@ def test_keys_past_2e31_delta_256():
     g = torch.Generator(device="cuda").manual_seed(2032)
     kin = torch.randint(-(1 << 31), 1 << 31, (n,), dtype=torch.int32, device="cuda",
                         generator=g)
-    ko, off = ms.keys(kin, m, ms.BucketFn.div(d))
+    fn = ms.BucketFn.div(d)
+    ko, off = ms.keys(kin, m, fn)
     torch.cuda.synchronize()
     check_stable_multisplit(kin, ko, None, off, n, m, "div", d)
-    # the key-only output holds the input's keys: equal sums (with the counts)
-    sin = sum(int(u32(kin[s:s + SLICE]).sum()) for s in range(0, n, SLICE))
-    sout = sum(int(u32(ko[s:s + SLICE]).sum()) for s in range(0, n, SLICE))
-    assert sin == sout
+    # The key-only output must equal the keys of the key-value output on the
+    # same keys with values = original index.  The key-value output is pinned
+    # to the unique stable multisplit by check_stable_multisplit (each value
+    # names its input key, values increase inside every bucket, counts
+    # match), so this pins the key-only output's multiset and its order
+    # inside every bucket too.
+    vin = torch.empty(n, dtype=torch.int32, device="cuda")
+    for s in range(0, n, SLICE):
+        e = min(n, s + SLICE)
+        vin[s:e] = torch.arange(s, e, dtype=torch.int64, device="cuda").to(torch.int32)
+    say("case large pairs (same keys) n=%d m=%d delta" % (n, m))
+    ko2, vo2, off2 = ms.pairs(kin, vin, m, fn)
+    torch.cuda.synchronize()
+    del vin
+    check_stable_multisplit(kin, ko2, vo2, off2, n, m, "div", d)
+    assert bool((off == off2).all())
+    for s in range(0, n, SLICE):
+        assert bool((ko[s:s + SLICE] == ko2[s:s + SLICE]).all()), "key-only differs at slice %d" % s
 
 
 def test_pairs_at_the_largest_size():

@@ -115,6 +115,40 @@ def test_gpu_fit_against_cpu_fit():
     np.testing.assert_array_equal(host(k), ek)
 
 
+def test_gpu_fit_with_labels():
+    """Labels passed in: the upper-bound labels give the GPU fit without
+    labels bit for bit; other labels (top byte of the key) match the
+    oracle's fit to the same labels within the fit tolerance; no splitters
+    are needed then."""
+    from paper_1701_01189_amd import binding as ms
+    keys, spl, fit = lognormal_setup(1 << 16, fit_n=(1 << 18) + 77)
+    ds, dfit = dev(spl), dev(fit)
+    say("case gpu fit with labels")
+    ub = np.searchsorted(spl, fit, side="right").astype(np.uint32)
+    g0 = ms.learned_fit(dfit, ds, 256).cpu().numpy()
+    g1 = ms.learned_fit(dfit, ds, 256, labels=dev(ub)).cpu().numpy()
+    np.testing.assert_array_equal(g0, g1)
+    lab = (fit >> np.uint32(24)).astype(np.uint32)
+    cpu = oracle.learned_fit(fit, spl, 256, labels=lab)
+    g2 = ms.learned_fit(dfit, None, 256, labels=dev(lab)).cpu().numpy()
+    np.testing.assert_allclose(g2, cpu, rtol=1e-5, atol=1e-12)
+
+
+def test_gpu_fit_degenerate_samples():
+    """All sample keys equal (zero key range), two distinct keys, and the
+    saturated top key only: the GPU fit matches the oracle's."""
+    from paper_1701_01189_amd import binding as ms
+    spl = np.sort(inputs.uniform_u32(61, 255))
+    for name, fit in (("equal", np.full(5000, 123456789, np.uint32)),
+                      ("two", np.array([7, 0xFFFFFFFF] * 3000, np.uint32)),
+                      ("top", np.full(4097, 0xFFFFFFFF, np.uint32)),
+                      ("one", np.array([0], np.uint32))):
+        say("case gpu fit degenerate %s" % name)
+        cpu = oracle.learned_fit(fit, spl, 256)
+        gpu = ms.learned_fit(dev(fit), dev(spl), 256).cpu().numpy()
+        np.testing.assert_allclose(gpu, cpu, rtol=1e-5, atol=1e-12)
+
+
 def test_range_2e27_lognormal_learned_full_size():
     """n = 2^27 lognormal(20, 2) saturated keys (seed 103), m = 256 buckets at
     quantiles of a 2^16-key sample (seed 1031); model fit on the GPU from 2^20

@@ -134,6 +134,26 @@ def test_several_chunks_per_group(shape, m):
         np.testing.assert_array_equal(host(o), eo)
 
 
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("m", [2, 32, 256])
+def test_several_chunks_per_group_keys(shape, m):
+    # Key-only tiles with many tiles per chunk: the running bucket bases are
+    # carried over the chunk's tiles (visited last to first by block and wave
+    # reordering) without values in the tile.
+    from paper_1701_01189_amd import binding as ms
+    n = 300_007
+    keys = inputs.uniform_u32(91 + m, n)
+    r = (m - 1).bit_length()
+    ek, _, eo = oracle.multisplit(keys, m, oracle.SHIFT_MASK, shift=32 - r, mask=m - 1)
+    for chunks in (1, 3, 7):
+        say("case keys chunks=%d m=%d shape=%s" % (chunks, m, shape))
+        opt = ms.Options(reorder=shape[0], waves_per_block=shape[1], items_per_lane=shape[2],
+                         max_chunks=chunks)
+        k, o = ms.keys(dev(keys), m, ms.BucketFn.shift_mask(32 - r, m - 1), options=opt)
+        np.testing.assert_array_equal(host(k), ek)
+        np.testing.assert_array_equal(host(o), eo)
+
+
 def test_empty_and_single_bucket():
     from paper_1701_01189_amd import binding as ms
     say("case n=0")

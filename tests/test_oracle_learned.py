@@ -107,3 +107,36 @@ def test_fit_uniform_recovers_linear_cdf():
     ids, miss = oracle.learned_bucket_ids(model, spl, m, keys)
     np.testing.assert_array_equal(ids, keys >> np.uint32(24))
     assert miss / len(keys) < 0.02
+
+
+def test_fit_with_given_labels():
+    # Labels passed in replace the upper bound: the upper-bound labels give
+    # the same model bit for bit, and other labels (here the top byte of the
+    # key, m = 256) give per-leaf least-squares lines of those labels.
+    m = 256
+    sample = inputs.lognormal_u32(1031, 1 << 16)
+    spl = inputs.quantile_splitters(sample, m)
+    fit = inputs.lognormal_u32(1032, 1 << 15)
+    ub = np.searchsorted(spl, fit, side="right").astype(np.uint32)
+    np.testing.assert_array_equal(oracle.learned_fit(fit, spl, m, labels=ub),
+                                  oracle.learned_fit(fit, spl, m))
+    lab = (fit >> np.uint32(24)).astype(np.uint32)
+    model = oracle.learned_fit(fit, spl, m, labels=lab)
+    x = fit.astype(np.float32).astype(np.float64)
+    y = lab.astype(np.float64) + 0.5
+    leaves = np.array([clamp_trunc(f32_fma_via_f64(model[0], np.float32(k), model[1]), 256)
+                       for k in x.astype(np.float32)])
+    checked = 0
+    for leaf in np.unique(leaves):
+        sel = leaves == leaf
+        if sel.sum() >= 2 and np.ptp(x[sel]) > 0 and np.ptp(y[sel]) > 0:
+            a, b = np.polyfit(x[sel], y[sel], 1)
+            np.testing.assert_allclose(model[2 + 2 * leaf], a, rtol=1e-4, atol=1e-12)
+            np.testing.assert_allclose(model[3 + 2 * leaf], b, rtol=1e-4, atol=2e-3)
+            checked += 1
+    assert checked > 20
+    # labels at or above m count as m - 1
+    big = np.full(len(fit), 1000, dtype=np.uint32)
+    np.testing.assert_array_equal(oracle.learned_fit(fit, spl, m, labels=big),
+                                  oracle.learned_fit(fit, spl, m,
+                                                     labels=np.full(len(fit), 255, np.uint32)))
