@@ -131,20 +131,22 @@ template <int Kind, int BITS, bool KV, int WPB, int NW>
 __global__ void __launch_bounds__(WPB* kWave) batched_kernel(BatchedArgs a) {
   constexpr int T = WPB * NW * kWave;
   constexpr int MB = Owned<BITS>::value;
-  __shared__ BucketLds tables;
+  constexpr bool TABLES = (Kind == kSplitters || Kind == kLearned);
+  __shared__ uint32_t s_tables[TABLES ? (sizeof(BucketLds) + 3) / 4 : 1];
   __shared__ uint32_t s_cnt[WPB * kCntStride];
   __shared__ uint32_t s_run[kMaxBuckets];
   __shared__ uint32_t s_delta[kMaxBuckets];
-  __shared__ uint32_t s_keys[T];
+  constexpr int SLOT = reorder_bytes_per_slot<(BITS <= 6), !TABLES>();
+  __shared__ uint64_t s_reorder[(T * SLOT + 7) / 8];
   __shared__ uint32_t s_vals[KV ? T : 1];
-  __shared__ uint8_t s_bk[T];
   __shared__ uint32_t s_tmp[WPB];
   __shared__ uint32_t s_next, s_flag;
 
-  stage_bucket_tables<Kind>(a.bp, &tables);
+  BucketLds* tables = reinterpret_cast<BucketLds*>(s_tables);
+  if (TABLES) stage_bucket_tables<Kind>(a.bp, tables);
   __syncthreads();
-  Bucket<Kind, BITS> bf_pre(a.bp, &tables);
-  Bucket<Kind, BITS> bf_post(a.bp, &tables);
+  Bucket<Kind, BITS> bf_pre(a.bp, tables);
+  Bucket<Kind, BITS> bf_post(a.bp, tables);
   const uint32_t lane = lane_id(), w = wave_id();
   const uint32_t tid = threadIdx.x;
   const LaneSel ls(lane);
@@ -303,16 +305,25 @@ __global__ void __launch_bounds__(WPB* kWave) batched_kernel(BatchedArgs a) {
       const uint32_t n_i = (uint32_t)(a.seg[i + 1] - s0);
       const uint32_t tcount = min((uint32_t)T, n_i - t * T);
       const uint32_t* Hi = a.H + (size_t)m * a.tile_start[i];
-      for (uint32_t b = tid; b < m; b += WPB * kWave) s_run[b] = s0 + Hi[b * tiles + t];
-      __syncthreads();
-      TileCtx<KV> ctx{s_keys, s_vals, s_bk, s_cnt + w * kCntStride, s_cnt, s_run, s_delta,
-                      s_tmp, a.keys_out, a.vals_out, m, tcount, w, lane, tid};
+      const TileBufs<KV> tb{s_reorder, s_vals, s_cnt, s_run, s_delta, s_tmp, a.keys_out,
+                            a.vals_out};
       // the next item's loads go out once this tile sits in LDS
       auto next = [&] { if (it + 1 < last) load_item(it + 1, std::true_type{}); };
-      if (tcount == (uint32_t)T)
-        tile_rank_reorder_write<BITS, KV, WPB, NW, true>(bf_post, k, v, ctx, next);
-      else
-        tile_rank_reorder_write<BITS, KV, WPB, NW, false>(bf_post, k, v, ctx, next);
+      if constexpr (BITS <= 6) {
+        // lane b of every wavefront holds bucket b's output position
+        uint32_t run = lane < m ? s0 + Hi[lane * tiles + t] : 0u;
+        if (tcount == (uint32_t)T)
+          tile_small<BITS, KV, WPB, NW, true, false>(bf_post, k, v, tb, tcount, w, lane, run, next);
+        else
+          tile_small<BITS, KV, WPB, NW, false, false>(bf_post, k, v, tb, tcount, w, lane, run, next);
+      } else {
+        for (uint32_t b = tid; b < m; b += WPB * kWave) s_run[b] = s0 + Hi[b * tiles + t];
+        __syncthreads();
+        if (tcount == (uint32_t)T)
+          tile_large<BITS, KV, WPB, NW, true, false>(bf_post, k, v, tb, m, tcount, w, lane, next);
+        else
+          tile_large<BITS, KV, WPB, NW, false, false>(bf_post, k, v, tb, m, tcount, w, lane, next);
+      }
       __syncthreads();
     }
   }

@@ -141,12 +141,22 @@ __device__ __forceinline__ void wave_order() { __builtin_amdgcn_fence(__ATOMIC_A
 // ---------------------------------------------------------------------------
 // scans
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v, uint32_t lane) {
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    uint32_t o = __shfl_up(v, d, kWave);
-    if (lane >= (uint32_t)d) v += o;
-  }
+// Inclusive scan over the 64 lanes with data-parallel primitives (DPP): four
+// row shifts (1, 2, 4, 8) scan each row of 16 lanes; broadcasting lane 15
+// into rows 1 and 3 and then lane 31 into rows 2 and 3 carries the row
+// totals across.  A lane whose DPP source is outside its row, or whose row
+// is masked off, receives the `old` operand, 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp_add(uint32_t v) {
+  return v + (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xF, false);
+}
+__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v, uint32_t /*lane*/) {
+  v = dpp_add<0x111, 0xF>(v);  // row_shr:1
+  v = dpp_add<0x112, 0xF>(v);  // row_shr:2
+  v = dpp_add<0x114, 0xF>(v);  // row_shr:4
+  v = dpp_add<0x118, 0xF>(v);  // row_shr:8
+  v = dpp_add<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+  v = dpp_add<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
   return v;
 }
 
@@ -183,6 +193,7 @@ struct Bucket;
 
 template <int BITS>
 struct Bucket<kShiftMask, BITS> {
+  static constexpr bool kCheap = true;  // recomputed from the key instead of stored
   uint32_t shift, mask;
   __device__ Bucket(const BucketParams& p, const BucketLds*) : shift(p.shift), mask(p.mask) {}
   __device__ __forceinline__ uint32_t operator()(uint32_t k) const { return (k >> shift) & mask; }
@@ -196,6 +207,7 @@ struct Bucket<kShiftMask, BITS> {
 // split in two passes (all ones otherwise).
 template <int BITS>
 struct Bucket<kDiv, BITS> {
+  static constexpr bool kCheap = true;
   uint32_t magic, sh1, sh2, mask;
   __device__ Bucket(const BucketParams& p, const BucketLds*)
       : magic(p.magic), sh1(p.sh1), sh2(p.sh2), mask(p.mask) {}
@@ -223,6 +235,7 @@ __device__ __forceinline__ uint32_t lds_upper_bound(const uint32_t* spl, uint32_
 
 template <int BITS>
 struct Bucket<kSplitters, BITS> {
+  static constexpr bool kCheap = false;  // an LDS search: computed once, then stored
   const uint32_t* spl;
   uint32_t m;
   __device__ Bucket(const BucketParams& p, const BucketLds* l) : spl(l->spl + kSplPad), m(p.m) {}
@@ -247,6 +260,7 @@ __device__ __forceinline__ uint32_t clamp_trunc(float v, uint32_t hi) {
 
 template <int BITS>
 struct Bucket<kLearned, BITS> {
+  static constexpr bool kCheap = false;
   const uint32_t* tbl;  // spl with the two zero words in front
   const float* model;
   uint32_t m;

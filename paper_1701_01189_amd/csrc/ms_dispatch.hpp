@@ -33,6 +33,7 @@ struct PostArgs {
   int mode, wpb, nw;
   bool kv;
   hipStream_t stream;
+  int* occupancy;  // if set: store the kernel's resident workgroups per CU, launch nothing
 };
 
 // Shapes with an instantiated post-scan: (mode, waves per block, windows).
@@ -87,10 +88,23 @@ template <int Kind, int BITS, bool KV, int WPB, int NW, int MODE>
 hipError_t post_launch(const PostArgs& a) {
   constexpr int WPG = (MODE == kBlock) ? WPB : 1;
   constexpr int GPB = WPB / WPG;
+  auto kern = postscan_kernel<Kind, BITS, KV, WPB, NW, MODE>;
+  if (a.occupancy) {
+    // The kernel's registers and LDS fix its residency; it is the same on
+    // every call, so it is asked once.
+    static int cached = 0;
+    if (cached == 0) {
+      int per_cu = 0;
+      hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, WPB * kWave, 0);
+      if (e != hipSuccess) return e;
+      cached = per_cu > 0 ? per_cu : 1;
+    }
+    *a.occupancy = cached;
+    return hipSuccess;
+  }
   dim3 grid((a.plan.L0 + GPB - 1) / GPB), block(WPB * kWave);
-  hipLaunchKernelGGL((postscan_kernel<Kind, BITS, KV, WPB, NW, MODE>), grid, block, 0, a.stream,
-                     a.keys_in, a.vals_in, a.keys_out, a.vals_out, a.G, a.totals, a.offsets,
-                     a.plan, a.bp);
+  hipLaunchKernelGGL(kern, grid, block, 0, a.stream, a.keys_in, a.vals_in, a.keys_out,
+                     a.vals_out, a.G, a.totals, a.offsets, a.plan, a.bp);
   return hipGetLastError();
 }
 

@@ -11,7 +11,7 @@
 
 #include <type_traits>
 
-#include "ms_device.hpp"
+#include "ms_tile.hpp"
 
 namespace ms {
 
@@ -24,47 +24,6 @@ struct Plan {
   uint32_t chunk;     // elements per chunk (multiple of the tile size)
   uint32_t tile;      // elements per tile
 };
-
-// ---------------------------------------------------------------------------
-// group barriers: a whole workgroup (BMS) or a single wavefront (WMS/DMS)
-// ---------------------------------------------------------------------------
-template <int WPG>
-__device__ __forceinline__ void group_sync() {
-  if (WPG > 1) {
-    __syncthreads();
-  } else {
-    // one wavefront: its LDS operations complete in order; only the
-    // compiler has to be kept from moving accesses across this point.
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  }
-}
-
-// Exclusive scan of one value per thread over a group of WPG wavefronts.
-// `tmp` holds WPG words of LDS private to the group.  Returns the exclusive
-// prefix; *total receives the group total.
-template <int WPG>
-__device__ __forceinline__ uint32_t group_exclusive_scan(uint32_t v, uint32_t* tmp, uint32_t wg,
-                                                         uint32_t lane, uint32_t* total) {
-  uint32_t inc = wave_inclusive_scan(v, lane);
-  if (WPG == 1) {
-    *total = wave_broadcast(inc, kWave - 1);
-    return inc - v;
-  }
-  if (lane == kWave - 1) tmp[wg] = inc;
-  group_sync<WPG>();
-  uint32_t before = 0, all = 0;
-#pragma unroll
-  for (int w = 0; w < WPG; ++w) {
-    uint32_t t = tmp[w];
-    before += (w < (int)wg) ? t : 0u;
-    all += t;
-  }
-  group_sync<WPG>();  // tmp may be reused right after
-  *total = all;
-  return before + inc - v;
-}
 
 // ---------------------------------------------------------------------------
 // Pre-scan: one column of H per chunk (Algorithm 1's pre-scan).  WPG
@@ -205,31 +164,6 @@ prescan_kernel(const uint32_t* __restrict__ keys, Plan plan, BucketParams bp,
   }
 }
 
-// ---------------------------------------------------------------------------
-// One tile of the post-scan (steps 2-5 below) for a group of WPG wavefronts
-// whose keys (and values) are already in registers k, v: element (wave wg,
-// window j, lane) of the tile is k[j] of that lane.  run[b] holds the output
-// position of the tile's first bucket-b element and is advanced past the
-// tile's bucket-b elements.  `after_stage` runs once k, v are no longer
-// needed (used to issue the next tile's loads early).
-// ---------------------------------------------------------------------------
-template <bool KV>
-struct TileCtx {
-  uint32_t* s_k;       // LDS reorder buffer: keys
-  uint32_t* s_v;       // LDS reorder buffer: values
-  uint8_t* s_b;        // LDS reorder buffer: bucket ids
-  uint32_t* my_cnt;    // this wavefront's counters [bucket]
-  uint32_t* grp_cnt;   // the group's counters [wave][bucket], stride CNT_STRIDE
-  uint32_t* run;       // [bucket] output position of the next element
-  uint32_t* delta;     // [bucket] scratch: output position minus LDS slot
-  uint32_t* tmp;       // WPG words for the group scan
-  uint32_t* keys_out;
-  uint32_t* vals_out;
-  uint32_t m, tcount, wg, lane, tid_g;
-};
-
-constexpr int kCntStride = kMaxBuckets + 1;
-
 // The post-scan visits a chunk's tiles last to first.  The pre-scan swept
 // every chunk first to last, so the last lines it read -- the ends of the
 // chunks -- are the ones still in the memory-side cache when the post-scan
@@ -239,129 +173,16 @@ constexpr int kCntStride = kMaxBuckets + 1;
 // forward order would (the tile's local order is unchanged).
 constexpr bool kReverseTiles = true;
 
-template <int BITS, bool KV, int WPG, int NW, bool FULL, class BF, class AfterStage,
-          bool REV = false>
-__device__ __forceinline__ void tile_rank_reorder_write(const BF& bf, uint32_t (&k)[NW],
-                                                        uint32_t (&v)[NW], const TileCtx<KV>& c,
-                                                        AfterStage after_stage) {
-  const uint32_t m = c.m, tcount = c.tcount, lane = c.lane, wg = c.wg, tid_g = c.tid_g;
-  const uint32_t wbase = wg * NW * kWave;
-  for (uint32_t b = lane; b < m; b += kWave) lds_put(c.my_cnt + b, 0u);
-  uint32_t bk[NW], lr[NW];
-#pragma unroll
-  for (int j = 0; j < NW; ++j) {
-    const bool valid = FULL || wbase + (uint32_t)(j * kWave) + lane < tcount;
-    bk[j] = valid ? bf(k[j]) : 0u;
-  }
-  wave_order();
-  // ranking: Algorithm 3 per window + per-wavefront running counts.  The
-  // next window's count is read right after this window's store (a
-  // wavefront's LDS operations complete in order), so the read's latency
-  // overlaps the next window's ballots instead of stalling after them.
-  uint32_t before = lds_get(c.my_cnt + bk[0]);
-#pragma unroll
-  for (int j = 0; j < NW; ++j) {
-    const bool valid = FULL || wbase + (uint32_t)(j * kWave) + lane < tcount;
-    const uint64_t mm = match_bucket<BITS>(bk[j], FULL ? ~0ull : ballot(valid));
-    const uint32_t r = count_below(mm), cnt = popc64(mm);
-    lr[j] = before + r;
-    // With values (more registers live), materialise the rank now: otherwise
-    // the compiler sinks it past the barriers and keeps both halves of every
-    // window's match mask alive instead (measured: 2^25 pairs, m = 32,
-    // post-scan 120 -> 110 us; key-only runs faster without it).
-    if (KV) asm("" : "+v"(lr[j]));
-    // Every lane of a bucket read the same `before` and holds the same
-    // count, so all of them store the same new value (no branch).  An
-    // invalid lane carries bucket 0 and counts the valid bucket-0 lanes, so
-    // it stores that same value too.
-    lds_put(c.my_cnt + bk[j], before + cnt);
-    wave_order();
-    if (j + 1 < NW) before = lds_get(c.my_cnt + bk[j + 1]);
-  }
-  group_sync<WPG>();
-  // exclusive scan of the bucket-major table: entry e = b*WPG + wave
-  {
-    const uint32_t E = m * WPG;
-    const uint32_t ept = (E + WPG * kWave - 1) / (WPG * kWave);
-    const uint32_t e0 = tid_g * ept;
-    uint32_t vals[4];
-    uint32_t s = 0;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const uint32_t e = e0 + i;
-      vals[i] = ((uint32_t)i < ept && e < E) ? c.grp_cnt[(e % WPG) * kCntStride + e / WPG] : 0u;
-      s += vals[i];
-    }
-    uint32_t total;
-    uint32_t pre = group_exclusive_scan<WPG>(s, c.tmp, wg, lane, &total);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const uint32_t e = e0 + i;
-      if ((uint32_t)i < ept && e < E) c.grp_cnt[(e % WPG) * kCntStride + e / WPG] = pre;
-      pre += vals[i];
-    }
-  }
-  group_sync<WPG>();
-  // tile bucket starts -> output delta; advance the running bases
-  for (uint32_t b = tid_g; b < m; b += WPG * kWave) {
-    const uint32_t st = c.grp_cnt[b];
-    const uint32_t nx = (b + 1 < m) ? c.grp_cnt[b + 1] : tcount;
-    if (REV) {  // tiles visited last to first: run[b] is the end of what is left
-      c.run[b] -= nx - st;
-      c.delta[b] = c.run[b] - st;
-    } else {
-      c.delta[b] = c.run[b] - st;
-      c.run[b] += nx - st;
-    }
-  }
-  // local reorder: slot = tile base of (bucket, wavefront) + rank
-#pragma unroll
-  for (int j = 0; j < NW; ++j) {
-    const bool valid = FULL || wbase + (uint32_t)(j * kWave) + lane < tcount;
-    if (valid) {
-      const uint32_t slot = c.my_cnt[bk[j]] + lr[j];
-      c.s_k[slot] = k[j];
-      if (KV) c.s_v[slot] = v[j];
-      c.s_b[slot] = (uint8_t)bk[j];
-    }
-  }
-  group_sync<WPG>();
-  after_stage();
-  // coalesced write-back: consecutive slots of a bucket are consecutive
-  // output positions
-#pragma unroll
-  for (int j = 0; j < NW; ++j) {
-    const uint32_t q = j * (WPG * kWave) + tid_g;
-    if (FULL || q < tcount) {
-      const uint32_t b = c.s_b[q];
-      const uint32_t o = c.delta[b] + q;
-      c.keys_out[o] = c.s_k[q];
-      if (KV) c.vals_out[o] = c.s_v[q];
-    }
-  }
-  group_sync<WPG>();
-}
-
 // ---------------------------------------------------------------------------
 // Post-scan (Algorithm 1's post-scan, Sections 5.5.3-5.6).
 //
-// For every tile of the group's chunk:
-//  1. each wavefront loads NW windows, element (wave wg, window j, lane l) at
-//     tile_base + (wg*NW + j)*64 + l -- so (wg, j, l) is input order;
-//  2. per window: match mask of the lane's bucket (Algorithm 3), rank among
-//     lower lanes, and a per-wavefront running count per bucket kept in LDS
-//     (every lane of a bucket stores the same new count): the first and
-//     second terms of Eq. (4);
-//  3. one exclusive scan over the bucket-major table [bucket][wavefront] of
-//     those counts gives, for wavefront wg and bucket b, the number of tile
-//     elements in buckets < b plus those of bucket b in earlier wavefronts --
-//     the tile-local destination base (third term of Eq. 4 plus the tile
-//     histogram scan of Section 5.6.2);
-//  4. write the element into its slot of the reorder buffer (a stable local
-//     multisplit of the tile, Section 4.7);
-//  5. read the buffer linearly; slot q of bucket b goes to
-//     G[b][chunk] + (elements of b in earlier tiles) + (q - tile start of b).
-// Mode kDirect skips 3-5 and writes from registers (DMS).
+// Each group (a workgroup for BMS, a wavefront for WMS/DMS) owns one chunk
+// and visits its tiles; a tile's loads are issued while the previous tile
+// is being written back.  The per-tile work (rank, bases, local reorder,
+// coalesced write-back) is tile_small / tile_large.  The output position of
+// bucket b's elements of chunk c starts at the bucket's base (exclusive scan
+// of the bucket totals, first term of Eq. 2) plus G[b][c] (second term).
+// Mode kDirect ranks the same way but writes from registers (DMS).
 // ---------------------------------------------------------------------------
 template <int Kind, int BITS, bool KV, int WPB, int NW, int MODE>
 __global__ void __launch_bounds__(WPB* kWave)
@@ -373,67 +194,89 @@ postscan_kernel(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict
   constexpr int GPB = WPB / WPG;
   constexpr int T = WPG * NW * kWave;
   constexpr bool REORDER = (MODE != kDirect);
-  constexpr int CNT_STRIDE = kCntStride;
+  constexpr bool SMALL = BITS <= 6;  // one bucket per lane
+  constexpr bool TABLES = (Kind == kSplitters || Kind == kLearned);
+  constexpr int S = SMALL ? kWave : kCntStride;  // counter row stride
+  constexpr bool REV = kReverseTiles && REORDER;
+  static_assert(SMALL || WPB * kWave >= kMaxBuckets, "one thread per bucket base");
 
-  __shared__ BucketLds tables;
-  __shared__ uint32_t s_cnt[WPB * CNT_STRIDE];           // per wavefront counts
-  __shared__ uint32_t s_run[GPB * kMaxBuckets];          // running output base
-  __shared__ uint32_t s_delta[REORDER ? GPB * kMaxBuckets : 1];
-  __shared__ uint32_t s_keys[REORDER ? GPB * T : 1];
+  __shared__ uint32_t s_tables[TABLES ? (sizeof(BucketLds) + 3) / 4 : 1];
+  __shared__ uint32_t s_cnt[WPB * S];
+  __shared__ uint32_t s_run[SMALL ? 1 : GPB * kMaxBuckets];
+  __shared__ uint32_t s_delta[(REORDER && !SMALL) ? GPB * kMaxBuckets : 1];
+  constexpr int SLOT = reorder_bytes_per_slot<SMALL, !TABLES>();
+  __shared__ uint64_t s_reorder[REORDER ? (GPB * T * SLOT + 7) / 8 : 1];
   __shared__ uint32_t s_vals[(REORDER && KV) ? GPB * T : 1];
-  __shared__ uint8_t s_bk[REORDER ? GPB * T : 1];
   __shared__ uint32_t s_tmp[WPB];
+  BucketLds* tables = reinterpret_cast<BucketLds*>(s_tables);
 
   const uint32_t lane = lane_id();
   const uint32_t w = wave_id();
   const uint32_t g = w / WPG, wg = w % WPG;
-  const uint32_t tid_g = wg * kWave + lane;
   const uint32_t m = plan.m;
+  const uint32_t c = blockIdx.x * GPB + g;
 
-  stage_bucket_tables<Kind>(bp, &tables);
+  if (TABLES) stage_bucket_tables<Kind>(bp, tables);
 
-  // Bucket bases: exclusive scan of the bucket totals (first term of Eq. 2),
-  // computed by every workgroup.  m <= 256 <= threads per workgroup.
-  {
+  // Running output position of each bucket in the group's chunk: the
+  // bucket's base plus G[b][c], or with tiles visited last to first the
+  // chunk's end (the next chunk's start, or the bucket's end for the last
+  // chunk).  Up to 64 buckets every wavefront scans the totals itself and
+  // keeps bucket b's position in lane b.
+  uint32_t run = 0;
+  if (SMALL) {
+    const uint32_t tot = lane < m ? totals[lane] : 0u;
+    const uint32_t bb = wave_inclusive_scan(tot, lane) - tot;
+    if (blockIdx.x == 0 && w == 0) {
+      if (lane < m) offsets[lane] = bb;
+      if (lane == 0) offsets[m] = plan.n;
+    }
+    if (c < plan.L0 && lane < m) {
+      if (REV)
+        run = bb + (c + 1 < plan.L0 ? G[lane * plan.L0 + c + 1] : tot);
+      else
+        run = bb + G[lane * plan.L0 + c];
+    }
+    if (TABLES) __syncthreads();
+  } else {
     uint32_t v = threadIdx.x < m ? totals[threadIdx.x] : 0u;
     uint32_t total;
     uint32_t pre = group_exclusive_scan<WPB>(v, s_tmp, w, lane, &total);
-    __syncthreads();
     if (threadIdx.x < m) {
       s_cnt[threadIdx.x] = pre;  // staged bucket base
       if (blockIdx.x == 0) offsets[threadIdx.x] = pre;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) offsets[m] = plan.n;
     __syncthreads();
-    // Running output position of each bucket in the group's chunk: its
-    // start, or with tiles visited last to first its end (the next chunk's
-    // start, or the bucket's end for the last chunk).
     for (uint32_t i = threadIdx.x; i < GPB * m; i += WPB * kWave) {
-      uint32_t gg = i / m, b = i % m;
-      uint32_t cc = blockIdx.x * GPB + gg;
+      const uint32_t gg = i / m, b = i % m;
+      const uint32_t cc = blockIdx.x * GPB + gg;
       uint32_t r = 0;
       if (cc < plan.L0) {
-        if (!kReverseTiles || MODE == kDirect)
-          r = s_cnt[b] + G[b * plan.L0 + cc];
-        else
+        if (REV)
           r = s_cnt[b] + (cc + 1 < plan.L0 ? G[b * plan.L0 + cc + 1] : totals[b]);
+        else
+          r = s_cnt[b] + G[b * plan.L0 + cc];
       }
       s_run[gg * kMaxBuckets + b] = r;
     }
     __syncthreads();
   }
 
-  Bucket<Kind, BITS> bf(bp, &tables);
-  const uint32_t c = blockIdx.x * GPB + g;
+  Bucket<Kind, BITS> bf(bp, tables);
   if (c >= plan.L0) return;  // only whole idle groups leave (never a BMS group)
   const uint32_t c0 = c * plan.chunk;
   const uint32_t len = min(plan.chunk, plan.n - c0);
-  uint32_t* my_cnt = s_cnt + w * CNT_STRIDE;
-  uint32_t* run = s_run + g * kMaxBuckets;
+  uint32_t* my_cnt = s_cnt + w * S;
+  uint32_t* grun = s_run + (SMALL ? 0 : g * kMaxBuckets);
 
   if (MODE == kDirect) {
     // DMS: counters are the running output positions of this wavefront.
-    for (uint32_t b = lane; b < m; b += kWave) lds_put(my_cnt + b, run[b]);
+    if (SMALL) {
+      lds_put(my_cnt + lane, run);
+    } else {
+      for (uint32_t b = lane; b < m; b += kWave) lds_put(my_cnt + b, grun[b]);
+    }
     wave_order();
     const uint32_t steps = (uint32_t)(((uint64_t)len + NW * kWave - 1) / (NW * kWave));
     for (uint32_t si = 0; si < steps; ++si) {
@@ -466,11 +309,14 @@ postscan_kernel(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict
       }
     }
   } else {
-    uint32_t* s_k = s_keys + g * T;
-    uint32_t* s_v = s_vals + (KV ? g * T : 0);
-    uint8_t* s_b = s_bk + g * T;
-    uint32_t* delta = s_delta + g * kMaxBuckets;
-    uint32_t* grp_cnt = s_cnt + (g * WPG) * CNT_STRIDE;
+    const TileBufs<KV> tb{reinterpret_cast<char*>(s_reorder) + (size_t)g * T * SLOT,
+                          s_vals + (KV ? g * T : 0),
+                          s_cnt + (g * WPG) * S,
+                          grun,
+                          s_delta + (SMALL ? 0 : g * kMaxBuckets),
+                          s_tmp + g * WPG,
+                          keys_out,
+                          vals_out};
     const uint32_t ntiles = (uint32_t)(((uint64_t)len + T - 1) / T);
     const uint32_t wbase = wg * NW * kWave;
     uint32_t k[NW], v[NW];
@@ -480,10 +326,10 @@ postscan_kernel(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict
     // always exists, and are masked out later.
     auto load = [&](uint32_t ti, auto full_tag) {
       constexpr bool FULL = decltype(full_tag)::value;
-      const uint32_t tb = c0 + ti * T;
+      const uint32_t tb0 = c0 + ti * T;
       const uint32_t tcount = FULL ? (uint32_t)T : min((uint32_t)T, len - ti * T);
-      const uint32_t* pk = keys_in + tb + wbase + lane;
-      const uint32_t* pv = vals_in + tb + wbase + lane;
+      const uint32_t* pk = keys_in + tb0 + wbase + lane;
+      const uint32_t* pv = vals_in + tb0 + wbase + lane;
 #pragma unroll
       for (int j = 0; j < NW; ++j) {
         if (FULL) {
@@ -491,8 +337,8 @@ postscan_kernel(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict
           if (KV) v[j] = __builtin_nontemporal_load(pv + j * kWave);
         } else {
           const bool valid = wbase + (uint32_t)(j * kWave) + lane < tcount;
-          k[j] = __builtin_nontemporal_load(valid ? pk + j * kWave : keys_in + tb);
-          if (KV) v[j] = __builtin_nontemporal_load(valid ? pv + j * kWave : vals_in + tb);
+          k[j] = __builtin_nontemporal_load(valid ? pk + j * kWave : keys_in + tb0);
+          if (KV) v[j] = __builtin_nontemporal_load(valid ? pv + j * kWave : vals_in + tb0);
         }
       }
     };
@@ -506,22 +352,22 @@ postscan_kernel(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict
     auto tile = [&](uint32_t ti, auto full_tag) {
       constexpr bool FULL = decltype(full_tag)::value;
       const uint32_t tcount = FULL ? (uint32_t)T : min((uint32_t)T, len - ti * T);
-      TileCtx<KV> ctx{s_k, s_v, s_b, my_cnt, grp_cnt, run, delta, s_tmp + g * WPG,
-                      keys_out, vals_out, m, tcount, wg, lane, tid_g};
       auto next = [&] {
-        if (kReverseTiles) {
+        if (REV) {
           if (ti > 0) load_tile(ti - 1);
         } else if (ti + 1 < ntiles) {
           load_tile(ti + 1);
         }
       };
-      tile_rank_reorder_write<BITS, KV, WPG, NW, FULL, decltype(bf), decltype(next),
-                              kReverseTiles>(bf, k, v, ctx, next);
+      if constexpr (SMALL)
+        tile_small<BITS, KV, WPG, NW, FULL, REV>(bf, k, v, tb, tcount, wg, lane, run, next);
+      else
+        tile_large<BITS, KV, WPG, NW, FULL, REV>(bf, k, v, tb, m, tcount, wg, lane, next);
     };
 
-    if (ntiles > 0) load_tile(kReverseTiles ? ntiles - 1 : 0);
+    if (ntiles > 0) load_tile(REV ? ntiles - 1 : 0);
     for (uint32_t it = 0; it < ntiles; ++it) {
-      const uint32_t ti = kReverseTiles ? ntiles - 1 - it : it;
+      const uint32_t ti = REV ? ntiles - 1 - it : it;
       if (len - ti * T >= (uint32_t)T)
         tile(ti, std::true_type{});
       else

@@ -9,6 +9,7 @@
 #include <stdint.h>
 #include <string.h>
 
+
 #include "multisplit.h"
 #include "ms_aux_kernels.hpp"
 #include "ms_learned.hpp"
@@ -43,16 +44,22 @@ uint32_t ceil_log2(uint32_t m) {
 
 bool shape_supported(const Shape& s) { return ms::post_shape_supported(s.mode, s.wpb, s.nw); }
 
-// Default: block-level reordering (BMS) with tiles sized so that bucket
-// runs stay long (fewer partial cache lines at run ends, which L2 must merge
-// with the next tile's writes): 4 wavefronts x 16 windows for m <= 64;
-// above, 16 x 8 (8192 elements) for bucket functions computed in registers
-// and 8 x 8 for those that search LDS tables (their extra registers make
-// the larger tile slower).  Measured on MI355X with 2^25 pairs, 2^28 keys,
-// 2^28-pair radix sort and 2^27 range keys.  The paper's own defaults are 8
-// warps x 4 windows of 32 (Section 6, "Parameters").  With wave-level or
-// no reordering the default is 8 x 8 (4 x 16 for wave level at m <= 64).
-int resolve_shape(const ms_options* opt, uint32_t m, int kind, Shape* s) {
+// Default: block-level reordering (BMS).  Tile shapes measured on MI355X
+// (2^28 keys and pairs, m = 2 .. 256, back-to-back calls):
+//  * key-only up to 4 buckets: 4 wavefronts x 16 windows; up to 64 buckets:
+//    8 x 8 (more resident wavefronts, same 4096-element tile);
+//  * key-value up to 64 buckets: 16 x 8 from 2^26 pairs on (8192-element
+//    tiles: longer bucket runs per tile at the scatter), 8 x 8 below (with
+//    one 16-wavefront workgroup per compute unit a smaller input gives each
+//    workgroup too few tiles);
+//  * above 64 buckets, 16 x 8 for bucket functions computed in registers
+//    (the run length of a bucket per tile falls to T/m, so the larger tile
+//    wins) and 8 x 8 for those that search LDS tables (their extra
+//    registers make the larger tile slower).
+// The paper's own defaults are 8 warps x 4 windows of 32 (Section 6,
+// "Parameters").  With wave-level or no reordering the default is 8 x 8
+// (4 x 16 for wave level at m <= 64).
+int resolve_shape(const ms_options* opt, size_t n, uint32_t m, int kind, bool kv, Shape* s) {
   const bool table_kind = kind == MS_BUCKET_SPLITTERS || kind == MS_BUCKET_LEARNED;
   s->mode = ms::kBlock;
   if (opt) {
@@ -61,8 +68,14 @@ int resolve_shape(const ms_options* opt, uint32_t m, int kind, Shape* s) {
     if (opt->reorder == MS_REORDER_NONE) s->mode = ms::kDirect;
   }
   if (s->mode == ms::kBlock) {
-    s->wpb = m <= 64 ? 4 : (table_kind ? 8 : 16);
-    s->nw = m <= 64 ? 16 : 8;
+    if (m <= 64) {
+      const bool big_kv = kv && n >= ((size_t)1 << 26);
+      s->wpb = big_kv ? 16 : (m <= 4 && !kv ? 4 : 8);
+      s->nw = big_kv ? 8 : (m <= 4 && !kv ? 16 : 8);
+    } else {
+      s->wpb = table_kind ? 8 : 16;
+      s->nw = 8;
+    }
   } else {
     s->wpb = (s->mode == ms::kWaveMode && m <= 64) ? 4 : 8;
     s->nw = (s->mode == ms::kWaveMode && m <= 64) ? 16 : 8;
@@ -84,38 +97,30 @@ int resolve_shape(const ms_options* opt, uint32_t m, int kind, Shape* s) {
   return shape_supported(*s) ? MS_OK : MS_ERR_UNSUPPORTED;
 }
 
-// Static LDS of one post-scan workgroup (mirrors the kernel's arrays); used
-// to estimate how many workgroups are resident per compute unit.
-size_t post_lds_bytes(const Shape& s, bool kv) {
-  int wpg = s.mode == ms::kBlock ? s.wpb : 1;
-  int gpb = s.wpb / wpg;
-  size_t T = (size_t)wpg * s.nw * ms::kWave;
-  bool reorder = s.mode != ms::kDirect;
-  size_t b = sizeof(ms::BucketLds) + (size_t)s.wpb * (ms::kMaxBuckets + 1) * 4 +
-             (size_t)gpb * ms::kMaxBuckets * 4 + (size_t)s.wpb * 4;
-  if (reorder) b += (size_t)gpb * ms::kMaxBuckets * 4 + (size_t)gpb * T * (4 + (kv ? 4 : 0) + 1);
-  return b;
-}
+// Chunks (columns of H) at most: bounds the workspace.
+constexpr uint32_t kMaxChunks = 4096;
+// The pre-scan runs one 8-wavefront workgroup per chunk: with at least four
+// per compute unit it keeps 32 wavefronts per unit streaming.
+constexpr uint32_t kMinChunks = 4 * kNumCUs;
 
-// Subproblems: chunks of consecutive tiles, about one per resident group so
-// that H stays small (Section 4.4: few first-level subproblems, large local
-// ones).
-Plan make_plan(size_t n, uint32_t m, const Shape& s, bool kv) {
+// Subproblems: chunks of consecutive tiles (Section 4.4: few first-level
+// subproblems, large local ones).  Their number is a whole multiple of the
+// post-scan groups resident at once (`groups`; 0 if unknown), at least
+// kMinChunks, so that every round of post-scan workgroups is a full one.
+Plan make_plan(size_t n, uint32_t m, const Shape& s, uint32_t groups) {
   Plan p;
   p.n = (uint32_t)n;
   p.m = m;
   int wpg = s.mode == ms::kBlock ? s.wpb : 1;
   p.tile = (uint32_t)(wpg * s.nw * ms::kWave);
   uint64_t tiles = (n + p.tile - 1) / p.tile;
-  uint32_t cap = s.max_chunks;
-  if (cap == 0) {
-    size_t lds = post_lds_bytes(s, kv);
-    uint32_t by_lds = (uint32_t)(kLdsPerCU / lds);
-    uint32_t by_waves = 32u / (uint32_t)s.wpb;
-    uint32_t blocks = by_lds < by_waves ? by_lds : by_waves;
-    if (blocks < 1) blocks = 1;
-    cap = kNumCUs * blocks * (uint32_t)(s.wpb / wpg);
+  uint32_t cap = kMaxChunks;
+  if (s.max_chunks) {
+    cap = s.max_chunks;
+  } else if (groups) {
+    cap = groups * ((kMinChunks + groups - 1) / groups);
   }
+  if (cap > kMaxChunks) cap = kMaxChunks;
   uint64_t L0 = tiles < cap ? tiles : cap;
   if (L0 == 0) L0 = 1;
   uint64_t tpc = (tiles + L0 - 1) / L0;
@@ -311,6 +316,36 @@ BatchWorkspace carve_batch(void* ws, size_t total, uint32_t m, uint32_t num, con
   return w;
 }
 
+// Compute units of the current device (asked once per device).
+uint32_t device_cus() {
+  static int cus[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return kNumCUs;
+  if (cus[dev] == 0) {
+    int c = 0;
+    if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c < 1)
+      c = (int)kNumCUs;
+    cus[dev] = c;
+  }
+  return (uint32_t)cus[dev];
+}
+
+// Post-scan groups of this shape resident at once on the device (0 if the
+// runtime cannot tell: the plan then takes the upper bound).
+uint32_t resident_groups(int kind, int bits, bool kv, const Shape& s) {
+  int occ = 0;
+  ms::PostArgs q;
+  memset(&q, 0, sizeof(q));
+  q.mode = s.mode;
+  q.wpb = s.wpb;
+  q.nw = s.nw;
+  q.kv = kv;
+  q.occupancy = &occ;
+  if (post_by_kind(kind, q, bits) != hipSuccess || occ < 1) return 0;
+  const int wpg = s.mode == ms::kBlock ? s.wpb : 1;
+  return device_cus() * (uint32_t)occ * (uint32_t)(s.wpb / wpg);
+}
+
 // The three stages for one multisplit on already validated arguments.
 ms_status run_multisplit(const uint32_t* ki, const uint32_t* vi, uint32_t* ko, uint32_t* vo,
                          uint32_t* offsets, size_t n, uint32_t m, const ms_bucket_fn* fn,
@@ -321,10 +356,10 @@ ms_status run_multisplit(const uint32_t* ki, const uint32_t* vi, uint32_t* ko, u
     if (fill(offsets, m + 1, 0, st) != hipSuccess) return MS_ERR_HIP;
     return MS_OK;
   }
-  Plan p = make_plan(n, m, s, kv);
+  const int bits = (int)ceil_log2(m);
+  Plan p = make_plan(n, m, s, resident_groups(fn->kind, bits, kv, s));
   Workspace w = carve(ws, p);
   BucketParams bp = make_params(fn, m, opt ? opt->d_mispredicts : nullptr, div_mask);
-  const int bits = (int)ceil_log2(m);
   if (record(opt, 0, st) != hipSuccess) return MS_ERR_HIP;
   ms::PreArgs pa{ki, p, bp, w.H, s.mode, s.hist, st};
   if (pre_by_kind(fn->kind, pa, bits) != hipSuccess) return MS_ERR_HIP;
@@ -336,7 +371,7 @@ ms_status run_multisplit(const uint32_t* ki, const uint32_t* vi, uint32_t* ko, u
   // offsets are written by workgroup 0 of the post-scan; a NULL offsets
   // pointer is redirected to the spare words after the bucket totals.
   uint32_t* off = offsets ? offsets : w.totals + ms::kMaxBuckets;
-  ms::PostArgs qa{ki, vi, ko, vo, w.H, w.totals, off, p, bp, s.mode, s.wpb, s.nw, kv, st};
+  ms::PostArgs qa{ki, vi, ko, vo, w.H, w.totals, off, p, bp, s.mode, s.wpb, s.nw, kv, st, nullptr};
   if (post_by_kind(fn->kind, qa, bits) != hipSuccess) return MS_ERR_HIP;
   if (record(opt, 3, st) != hipSuccess) return MS_ERR_HIP;
   return MS_OK;
@@ -415,8 +450,8 @@ size_t wide_ws_bytes(size_t n, uint32_t m, bool kv, const ms_options* opt) {
   for (uint32_t mm : ms_)
     for (int kd : kinds) {
       Shape s;
-      if (resolve_shape(opt, mm, kd, &s) != MS_OK) return 0;
-      size_t b = ms_ws_bytes(make_plan(n, mm, s, kv));
+      if (resolve_shape(opt, n, mm, kd, kv, &s) != MS_OK) return 0;
+      size_t b = ms_ws_bytes(make_plan(n, mm, s, 0));
       if (b > best) best = b;
     }
   return data + best;
@@ -437,9 +472,9 @@ ms_status run_wide(const uint32_t* ki, const uint32_t* vi, uint32_t* ko, uint32_
     b += align_up(n * 4, kWsAlign);
   }
   Shape s_lo, s_hi;
-  int r = resolve_shape(opt, w.m_lo, w.lo.kind, &s_lo);
+  int r = resolve_shape(opt, n, w.m_lo, w.lo.kind, kv, &s_lo);
   if (r != MS_OK) return (ms_status)r;
-  r = resolve_shape(opt, w.m_hi, w.hi.kind, &s_hi);
+  r = resolve_shape(opt, n, w.m_hi, w.hi.kind, kv, &s_hi);
   if (r != MS_OK) return (ms_status)r;
   ms_options o;
   memset(&o, 0, sizeof(o));
@@ -490,8 +525,9 @@ size_t ms_workspace_size(int op, size_t n, uint32_t m, uint32_t num_inst, const 
     if (m > kMaxBucketsWide || n >= 0xFFFFFFFFull) return 0;
     return wide_ws_bytes(n, m, op == MS_OP_PAIRS, opt);
   }
+  const bool kv_op = op == MS_OP_PAIRS || op == MS_OP_RADIX_SORT_PAIRS;
   Shape s;  // radix passes use shift/mask buckets
-  if (resolve_shape(opt, m, MS_BUCKET_SHIFT_MASK, &s) != MS_OK) return 0;
+  if (resolve_shape(opt, n, m, MS_BUCKET_SHIFT_MASK, kv_op, &s) != MS_OK) return 0;
   switch (op) {
     case MS_OP_KEYS:
     case MS_OP_PAIRS:
@@ -499,9 +535,9 @@ size_t ms_workspace_size(int op, size_t n, uint32_t m, uint32_t num_inst, const 
       if (m < 1 || m > (uint32_t)ms::kMaxBuckets || n >= 0xFFFFFFFFull) return 0;
       // The default shape depends on the bucket kind: size for both.
       Shape t;
-      if (resolve_shape(opt, m, MS_BUCKET_SPLITTERS, &t) != MS_OK) return 0;
-      const size_t a = ms_ws_bytes(make_plan(n, m, s, op == MS_OP_PAIRS));
-      const size_t b = ms_ws_bytes(make_plan(n, m, t, op == MS_OP_PAIRS));
+      if (resolve_shape(opt, n, m, MS_BUCKET_SPLITTERS, kv_op, &t) != MS_OK) return 0;
+      const size_t a = ms_ws_bytes(make_plan(n, m, s, 0));
+      const size_t b = ms_ws_bytes(make_plan(n, m, t, 0));
       return a > b ? a : b;
     }
     case MS_OP_RADIX_SORT:
@@ -510,7 +546,7 @@ size_t ms_workspace_size(int op, size_t n, uint32_t m, uint32_t num_inst, const 
       if (n >= 0xFFFFFFFFull || m < 2 || m > (uint32_t)ms::kMaxBuckets || (m & (m - 1))) return 0;
       bool kv = op == MS_OP_RADIX_SORT_PAIRS;
       size_t data = align_up(n * 4, kWsAlign) * (kv ? 2 : 1);
-      return data + ms_ws_bytes(make_plan(n, m, s, kv));
+      return data + ms_ws_bytes(make_plan(n, m, s, 0));
     }
     case MS_OP_BATCHED: {
       if (m < 1 || m > (uint32_t)ms::kMaxBuckets || n >= 0xFFFFFFFFull || num_inst == 0) return 0;
@@ -553,7 +589,7 @@ ms_status ms_pairs(const uint32_t* d_keys_in, const uint32_t* d_vals_in, uint32_
                     fn, d_ws, opt, (hipStream_t)stream);
   }
   Shape s;
-  int sr = resolve_shape(opt, m, fn->kind, &s);
+  int sr = resolve_shape(opt, n, m, fn->kind, kv, &s);
   if (sr != MS_OK) return (ms_status)sr;
   size_t need = ms_workspace_size(kv ? MS_OP_PAIRS : MS_OP_KEYS, n, m, 0, opt);
   if (n > 0 && (!d_ws || ws_bytes < need)) return MS_ERR_WORKSPACE;
@@ -575,7 +611,7 @@ ms_status ms_histogram(const uint32_t* d_keys, size_t n, uint32_t m, const ms_bu
   int fr = validate_fn(fn, m);
   if (fr != MS_OK) return (ms_status)fr;
   Shape s;
-  int sr = resolve_shape(opt, m, fn->kind, &s);
+  int sr = resolve_shape(opt, n, m, fn->kind, false, &s);
   if (sr != MS_OK) return (ms_status)sr;
   const size_t need = ms_workspace_size(MS_OP_HISTOGRAM, n, m, 0, opt);
   if (n > 0 && (!d_ws || ws_bytes < need)) return MS_ERR_WORKSPACE;
@@ -586,7 +622,7 @@ ms_status ms_histogram(const uint32_t* d_keys, size_t n, uint32_t m, const ms_bu
   // The first is used: with ~2^11 subproblems, the atomic additions to each
   // bin serialise in L2 (2^25 keys, m = 32: 245 us against 25 us).  Here the
   // reduction is the row-total output of the scan kernel.
-  Plan p = make_plan(n, m, s, false);
+  Plan p = make_plan(n, m, s, resident_groups(fn->kind, (int)ceil_log2(m), false, s));
   Workspace w = carve(d_ws, p);
   BucketParams bp = make_params(fn, m, nullptr);
   if (record(opt, 0, st) != hipSuccess) return MS_ERR_HIP;
@@ -611,7 +647,7 @@ ms_status ms_radix_sort(const uint32_t* d_keys_in, const uint32_t* d_vals_in,
   ms_status rc = check_common(d_keys_in, d_vals_in, d_keys_out, d_vals_out, n, m_digit, kv);
   if (rc != MS_OK) return rc;
   Shape s;
-  int sr = resolve_shape(opt, m_digit, MS_BUCKET_SHIFT_MASK, &s);
+  int sr = resolve_shape(opt, n, m_digit, MS_BUCKET_SHIFT_MASK, kv, &s);
   if (sr != MS_OK) return (ms_status)sr;
   size_t need =
       ms_workspace_size(kv ? MS_OP_RADIX_SORT_PAIRS : MS_OP_RADIX_SORT, n, m_digit, 0, opt);
