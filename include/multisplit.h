@@ -224,6 +224,26 @@ ms_status ms_pairs(const uint32_t* d_keys_in, const uint32_t* d_vals_in,
                    const ms_options* opt, void* stream);
 
 /*
+ * ms_pairs (or ms_keys, with both value pointers NULL) for callers that
+ * cannot allocate device memory: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation.  It takes no workspace
+ * and allocates nothing: its scratch words (the bucket totals and the
+ * subproblem histograms H, at most 4 MiB) live in a static device array of
+ * the library, one per GPU, held until the process ends.  Arguments,
+ * results and errors are those of ms_pairs, plus:
+ *   m above 256   MS_ERR_WORKSPACE (that path needs a copy of the data).
+ * The first call on a device looks the array up (MS_ERR_HIP if that
+ * fails).  Calls share the device's array, so calls that overlap on one GPU
+ * (on different streams, or from different threads) race: serialise them.
+ * Every word the call reads is first written by the same call.
+ */
+ms_status ms_pairs_noalloc(const uint32_t* d_keys_in, const uint32_t* d_vals_in,
+                           uint32_t* d_keys_out, uint32_t* d_vals_out,
+                           uint32_t* d_offsets, size_t n, uint32_t m,
+                           const ms_bucket_fn* fn, const ms_options* opt,
+                           void* stream);
+
+/*
  * Device-wide histogram (Section 7.3): d_hist[j] = number of the n keys with
  * fn(key) = j, for j < m.  It is the multisplit pre-scan (one count per
  * bucket and subproblem), followed by a per-bucket reduction of those counts

@@ -54,6 +54,7 @@ class OptionsC(ctypes.Structure):
 
 _lib = None
 SYMBOLS = ["ms_status_str", "ms_version", "ms_workspace_size", "ms_keys", "ms_pairs",
+           "ms_pairs_noalloc",
            "ms_radix_sort", "ms_batched", "ms_batched_status", "ms_learned_fit", "ms_copy_u32",
            "ms_autotune", "ms_sssp", "ms_sssp_workspace_size"]
 
@@ -80,6 +81,9 @@ def lib():
     L.ms_pairs.argtypes = [vp, vp, vp, vp, vp, sz, u32, ctypes.POINTER(BucketFnC), vp, sz,
                            ctypes.POINTER(OptionsC), vp]
     L.ms_pairs.restype = i32
+    L.ms_pairs_noalloc.argtypes = [vp, vp, vp, vp, vp, sz, u32, ctypes.POINTER(BucketFnC),
+                                   ctypes.POINTER(OptionsC), vp]
+    L.ms_pairs_noalloc.restype = i32
     L.ms_histogram.argtypes = [vp, sz, u32, ctypes.POINTER(BucketFnC), vp, vp, sz,
                                ctypes.POINTER(OptionsC), vp]
     L.ms_histogram.restype = i32
@@ -248,6 +252,27 @@ def pairs(keys_in, vals_in, m, fn, keys_out=None, vals_out=None, offsets=None, o
                         _u32(offsets, "offsets"), n, m, ctypes.byref(f), _ptr(w), wb,
                         ctypes.byref(o) if o is not None else None, _stream(stream))
     _check(rc, "ms_pairs")
+    return keys_out, vals_out, offsets
+
+
+def pairs_noalloc(keys_in, vals_in, m, fn, keys_out, vals_out, offsets, options=None,
+                  stream=None):
+    """ms_pairs_noalloc: the stable multisplit without a workspace (the
+    library's static device array serves).  vals_in / vals_out None: key
+    only.  The caller passes every output; nothing is allocated."""
+    n = keys_in.numel()
+    if vals_in is not None and vals_in.numel() != n:
+        raise ValueError("keys and values differ in length")
+    f = fn.c()
+    o = options.c() if options is not None else None
+    rc = lib().ms_pairs_noalloc(_u32(keys_in, "keys_in"),
+                                _u32(vals_in, "vals_in") if vals_in is not None else None,
+                                _u32(keys_out, "keys_out"),
+                                _u32(vals_out, "vals_out") if vals_out is not None else None,
+                                _u32(offsets, "offsets") if offsets is not None else None,
+                                n, m, ctypes.byref(f),
+                                ctypes.byref(o) if o is not None else None, _stream(stream))
+    _check(rc, "ms_pairs_noalloc")
     return keys_out, vals_out, offsets
 
 

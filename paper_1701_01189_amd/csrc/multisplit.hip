@@ -9,6 +9,7 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <mutex>
 
 #include "multisplit.h"
 #include "ms_aux_kernels.hpp"
@@ -500,6 +501,33 @@ ms_status run_wide(const uint32_t* ki, const uint32_t* vi, uint32_t* ko, uint32_
   return MS_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Workspace of ms_pairs_noalloc: a file-scope device array.  Up to 256
+// buckets a multisplit needs the bucket totals and spare offsets (a few KiB)
+// plus H, m x L0 words with L0 <= kMaxChunks: at most 4 MiB whatever n.
+// Every GPU the library runs on holds its own copy until the process ends.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = kWsHeader + (size_t)ms::kMaxBuckets * kMaxChunks * 4;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_lock;
+void* g_scratch[kMaxDevices];  // device address of `scratch`, per device
+
+// The array's address on the current device, asked once per device (in host
+// code `scratch` itself only stands in for the symbol).
+void* scratch_on_current_device() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> hold(g_scratch_lock);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+    g_scratch[dev] = p;
+  }
+  return g_scratch[dev];
+}
+
 }  // namespace
 
 extern "C" {
@@ -595,6 +623,29 @@ ms_status ms_pairs(const uint32_t* d_keys_in, const uint32_t* d_vals_in, uint32_
   if (n > 0 && (!d_ws || ws_bytes < need)) return MS_ERR_WORKSPACE;
   return run_multisplit(d_keys_in, kv ? d_vals_in : nullptr, d_keys_out, d_vals_out, d_offsets,
                         n, m, fn, d_ws, s, opt, (hipStream_t)stream);
+}
+
+ms_status ms_pairs_noalloc(const uint32_t* d_keys_in, const uint32_t* d_vals_in,
+                           uint32_t* d_keys_out, uint32_t* d_vals_out, uint32_t* d_offsets,
+                           size_t n, uint32_t m, const ms_bucket_fn* fn, const ms_options* opt,
+                           void* stream) {
+  bool kv = d_vals_in != nullptr || d_vals_out != nullptr;
+  ms_status rc = check_common(d_keys_in, d_vals_in, d_keys_out, d_vals_out, n, m, kv,
+                              kMaxBucketsWide);
+  if (rc != MS_OK) return rc;
+  int fr = validate_fn(fn, m);
+  if (fr != MS_OK) return (ms_status)fr;
+  // more than 256 buckets need a copy of the data: beyond the static array
+  if (m > (uint32_t)ms::kMaxBuckets) return MS_ERR_WORKSPACE;
+  Shape s;
+  int sr = resolve_shape(opt, n, m, fn->kind, kv, &s);
+  if (sr != MS_OK) return (ms_status)sr;
+  if (ms_workspace_size(kv ? MS_OP_PAIRS : MS_OP_KEYS, n, m, 0, opt) > kScratchBytes)
+    return MS_ERR_WORKSPACE;
+  void* ws = scratch_on_current_device();
+  if (!ws) return MS_ERR_HIP;
+  return run_multisplit(d_keys_in, kv ? d_vals_in : nullptr, d_keys_out, d_vals_out, d_offsets,
+                        n, m, fn, ws, s, opt, (hipStream_t)stream);
 }
 
 ms_status ms_histogram(const uint32_t* d_keys, size_t n, uint32_t m, const ms_bucket_fn* fn,
