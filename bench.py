@@ -675,8 +675,9 @@ def row_config5(args, dev, ceiling, bits=8, kv=True):
     vals = inputs.index_values(n) if kv else None
     dk, dv = keys_device(keys, vals, dev)
     name = "radix_%s_2e28" % ("pairs" if kv else "keys") + ("" if bits == 8 else "_b%d" % bits)
-    return multisplit_row(args, name, dk, dv, 0, None, ceiling=ceiling, radix_bits=bits,
-                          tune=True,
+    shape = (args.reorder, args.waves, args.items)
+    return multisplit_row(args, name, dk, dv, 0, None, shape=shape, ceiling=ceiling,
+                          radix_bits=bits, tune=True,
                           cpu=lambda: cpu_baseline("radix", keys, vals, 0, 0,
                                                    args.row_cpu_seconds, 1 << 22))
 

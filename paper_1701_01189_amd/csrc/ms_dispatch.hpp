@@ -40,7 +40,7 @@ struct PostArgs {
 inline bool post_shape_supported(int mode, int wpb, int nw) {
   if (mode == kBlock)
     return (wpb == 8 && (nw == 4 || nw == 8)) || (wpb == 4 && (nw == 8 || nw == 16)) ||
-           (wpb == 16 && nw == 8);
+           (wpb == 16 && (nw == 8 || nw == 16));
   if (mode == kWaveMode) return (wpb == 8 && nw == 8) || (wpb == 4 && nw == 16);
   if (mode == kDirect) return wpb == 8 && nw == 8;
   return false;
@@ -114,6 +114,12 @@ hipError_t post_shape(const PostArgs& a) {
     if (a.wpb == 8 && a.nw == 8) return post_launch<Kind, BITS, KV, 8, 8, kBlock>(a);
     if (a.wpb == 8 && a.nw == 4) return post_launch<Kind, BITS, KV, 8, 4, kBlock>(a);
     if (a.wpb == 16 && a.nw == 8) return post_launch<Kind, BITS, KV, 16, 8, kBlock>(a);
+    if (a.wpb == 16 && a.nw == 16) {
+      // (16384-element key-value tiles up to 64 buckets do not fit in LDS)
+      if constexpr (postscan_lds_bytes<Kind, BITS, KV, 16, 16, kBlock>() <= kLdsLimit)
+        return post_launch<Kind, BITS, KV, 16, 16, kBlock>(a);
+      return hipErrorInvalidValue;
+    }
     if (a.wpb == 4 && a.nw == 8) return post_launch<Kind, BITS, KV, 4, 8, kBlock>(a);
     if (a.wpb == 4 && a.nw == 16) return post_launch<Kind, BITS, KV, 4, 16, kBlock>(a);
   } else if (a.mode == kWaveMode) {

@@ -184,6 +184,23 @@ constexpr bool kReverseTiles = true;
 // of the bucket totals, first term of Eq. 2) plus G[b][c] (second term).
 // Mode kDirect ranks the same way but writes from registers (DMS).
 // ---------------------------------------------------------------------------
+// Static LDS bytes of a post-scan instantiation (the arrays declared in
+// postscan_kernel, same rounding), for shapes that do not fit a CU.
+template <int Kind, int BITS, bool KV, int WPB, int NW, int MODE>
+constexpr size_t postscan_lds_bytes() {
+  constexpr int WPG = (MODE == kBlock) ? WPB : 1;
+  constexpr size_t GPB = WPB / WPG, T = (size_t)WPG * NW * kWave;
+  constexpr bool REORDER = MODE != kDirect, SMALL = BITS <= 6;
+  constexpr bool TABLES = (Kind == kSplitters || Kind == kLearned);
+  constexpr size_t SLOT = reorder_bytes_per_slot<SMALL, !TABLES>();
+  return (TABLES ? (sizeof(BucketLds) + 3) / 4 * 4 : 4) +
+         (size_t)WPB * (SMALL ? kWave : kCntStride) * 4 + (SMALL ? 4 : GPB * kMaxBuckets * 4) +
+         ((REORDER && !SMALL) ? GPB * kMaxBuckets * 4 : 4) +
+         (REORDER ? (GPB * T * SLOT + 7) / 8 * 8 : 8) + ((REORDER && KV) ? GPB * T * 4 : 4) +
+         (size_t)WPB * 4;
+}
+constexpr size_t kLdsLimit = 160 * 1024;
+
 template <int Kind, int BITS, bool KV, int WPB, int NW, int MODE>
 __global__ void __launch_bounds__(WPB* kWave)
 postscan_kernel(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,

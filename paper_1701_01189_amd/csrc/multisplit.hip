@@ -45,6 +45,27 @@ uint32_t ceil_log2(uint32_t m) {
 
 bool shape_supported(const Shape& s) { return ms::post_shape_supported(s.mode, s.wpb, s.nw); }
 
+constexpr size_t kLdsPerWorkgroup = 160 * 1024;  // gfx950: all of a CU's LDS
+
+// Static LDS of one post-scan workgroup (mirrors postscan_kernel's arrays).
+size_t post_lds_bytes(const Shape& s, uint32_t m, int kind, bool kv) {
+  const bool small = m <= 64;
+  const bool tables = kind == MS_BUCKET_SPLITTERS || kind == MS_BUCKET_LEARNED;
+  const bool reorder = s.mode != ms::kDirect;
+  const size_t wpg = s.mode == ms::kBlock ? (size_t)s.wpb : 1;
+  const size_t gpb = (size_t)s.wpb / wpg;
+  const size_t T = wpg * (size_t)s.nw * ms::kWave;
+  const size_t slot = small ? 8 : (4 + (tables ? 1 : 0));
+  size_t b = tables ? sizeof(ms::BucketLds) : 4;
+  b += (size_t)s.wpb * (small ? ms::kWave : ms::kCntStride) * 4;
+  b += small ? 4 : gpb * ms::kMaxBuckets * 4;
+  b += (reorder && !small) ? gpb * ms::kMaxBuckets * 4 : 4;
+  b += reorder ? (gpb * T * slot + 7) / 8 * 8 : 8;
+  b += (reorder && kv) ? gpb * T * 4 : 4;
+  b += (size_t)s.wpb * 4;
+  return b;
+}
+
 // Default: block-level reordering (BMS).  Tile shapes measured on MI355X
 // (2^28 keys and pairs, m = 2 .. 256, back-to-back calls):
 //  * key-only up to 4 buckets: 4 wavefronts x 16 windows; up to 64 buckets:
@@ -53,10 +74,12 @@ bool shape_supported(const Shape& s) { return ms::post_shape_supported(s.mode, s
 //    tiles: longer bucket runs per tile at the scatter), 8 x 8 below (with
 //    one 16-wavefront workgroup per compute unit a smaller input gives each
 //    workgroup too few tiles);
-//  * above 64 buckets, 16 x 8 for bucket functions computed in registers
-//    (the run length of a bucket per tile falls to T/m, so the larger tile
-//    wins) and 8 x 8 for those that search LDS tables (their extra
-//    registers make the larger tile slower).
+//  * above 64 buckets, for bucket functions computed in registers, 16 x 16
+//    from 2^26 elements on and 16 x 8 below: a bucket's run per tile is T/m
+//    elements, and the partial cache lines at the ends of the runs cost
+//    about 5000 us x m/T at 2^28 keys (m = 256: 906, 762 and 667 us for
+//    T = 4096, 8192 and 16384); 8 x 8 for bucket functions that search LDS
+//    tables (their extra registers make the larger tiles slower).
 // The paper's own defaults are 8 warps x 4 windows of 32 (Section 6,
 // "Parameters").  With wave-level or no reordering the default is 8 x 8
 // (4 x 16 for wave level at m <= 64).
@@ -75,7 +98,7 @@ int resolve_shape(const ms_options* opt, size_t n, uint32_t m, int kind, bool kv
       s->nw = big_kv ? 8 : (m <= 4 && !kv ? 16 : 8);
     } else {
       s->wpb = table_kind ? 8 : 16;
-      s->nw = 8;
+      s->nw = (!table_kind && n >= ((size_t)1 << 26)) ? 16 : 8;
     }
   } else {
     s->wpb = (s->mode == ms::kWaveMode && m <= 64) ? 4 : 8;
@@ -95,7 +118,10 @@ int resolve_shape(const ms_options* opt, size_t n, uint32_t m, int kind, bool kv
   if (prescan == MS_PRESCAN_LANES && s->mode != ms::kBlock) return MS_ERR_UNSUPPORTED;
   s->hist = (prescan == MS_PRESCAN_BALLOT || s->mode != ms::kBlock) ? ms::kHistBallot
                                                                      : ms::kHistLanes;
-  return shape_supported(*s) ? MS_OK : MS_ERR_UNSUPPORTED;
+  if (!shape_supported(*s)) return MS_ERR_UNSUPPORTED;
+  // a tile whose buffers do not fit in LDS (16 x 16 key-value up to 64 buckets)
+  if (post_lds_bytes(*s, m, kind, kv) > kLdsPerWorkgroup) return MS_ERR_UNSUPPORTED;
+  return MS_OK;
 }
 
 // Chunks (columns of H) at most: bounds the workspace.
@@ -561,10 +587,11 @@ size_t ms_workspace_size(int op, size_t n, uint32_t m, uint32_t num_inst, const 
     case MS_OP_PAIRS:
     case MS_OP_HISTOGRAM: {
       if (m < 1 || m > (uint32_t)ms::kMaxBuckets || n >= 0xFFFFFFFFull) return 0;
-      // The default shape depends on the bucket kind: size for both.
+      // The default shape depends on the bucket kind: size for both (a
+      // shape that table-search kinds cannot run is sized for the others).
       Shape t;
-      if (resolve_shape(opt, n, m, MS_BUCKET_SPLITTERS, kv_op, &t) != MS_OK) return 0;
       const size_t a = ms_ws_bytes(make_plan(n, m, s, 0));
+      if (resolve_shape(opt, n, m, MS_BUCKET_SPLITTERS, kv_op, &t) != MS_OK) return a;
       const size_t b = ms_ws_bytes(make_plan(n, m, t, 0));
       return a > b ? a : b;
     }
@@ -844,7 +871,7 @@ ms_status ms_autotune(int op, const uint32_t* d_keys_in, const uint32_t* d_vals_
   struct Cand { int reorder, wpb, nw; uint32_t claim; };
   static const Cand kMulti[] = {{MS_REORDER_BLOCK, 8, 8, 0},  {MS_REORDER_BLOCK, 8, 4, 0},
                                 {MS_REORDER_BLOCK, 4, 8, 0},  {MS_REORDER_BLOCK, 4, 16, 0},
-                                {MS_REORDER_BLOCK, 16, 8, 0},
+                                {MS_REORDER_BLOCK, 16, 8, 0}, {MS_REORDER_BLOCK, 16, 16, 0},
                                 {MS_REORDER_WAVE, 8, 8, 0},   {MS_REORDER_WAVE, 4, 16, 0},
                                 {MS_REORDER_NONE, 8, 8, 0}};
   static const Cand kBatch[] = {{MS_REORDER_BLOCK, 8, 8, 1},  {MS_REORDER_BLOCK, 8, 8, 4},
