@@ -352,10 +352,13 @@ def autotune(op, keys_in, vals_in, m, fn=None, seg=None, reps=3, base=None, stre
     vo = torch.empty_like(vals_in) if vals_in is not None else None
     radix = op in (OP_RADIX_SORT, OP_RADIX_SORT_PAIRS)
     need = 0
-    for wpb, nw, mode in ((8, 8, 1), (8, 4, 1), (4, 8, 1), (4, 16, 1), (16, 8, 1), (8, 8, 2),
-                          (4, 16, 2), (8, 8, 3)):
-        if op == OP_BATCHED and (wpb != 8 or mode != 1):
-            continue
+    # the workspace of the largest candidate (ms_autotune's lists; a shape
+    # the operation does not have sizes to 0)
+    shapes = ((8, 8, 1), (8, 4, 1), (4, 8, 1), (4, 16, 1), (16, 8, 1), (16, 16, 1), (8, 8, 2),
+              (4, 16, 2), (8, 8, 3))
+    if op == OP_BATCHED:
+        shapes = ((8, 8, 1), (8, 4, 1), (4, 16, 1), (4, 8, 1), (16, 4, 1), (16, 8, 1))
+    for wpb, nw, mode in shapes:
         need = max(need, workspace_size(op, n, (1 << m) if radix else m, num,
                                         Options(reorder=mode, waves_per_block=wpb,
                                                 items_per_lane=nw)))

@@ -33,7 +33,7 @@ struct BatchedArgs {
   uint32_t m;
   uint32_t* offsets;     // num * (m+1)
   uint32_t* tile_start;  // num + 1: first global tile of each instance
-  uint32_t* tile_inst;   // per global tile: its instance
+  uint4* tile_info;      // per global tile: first key, key count, instance, tile index
   uint32_t* H;           // m * P words; instance i at m * tile_start[i]
   uint32_t* done;        // num: finished pre-scan tiles
   uint32_t* ready;       // num: 1 once G of the instance is published
@@ -46,6 +46,7 @@ struct BatchedArgs {
 };
 
 constexpr int kSetupThreads = 1024;
+constexpr int kMaxClaim = 64;  // work items per queue claim, at most
 
 // (Internal linkage: every translation unit that launches it has a copy.)
 // Tiles per instance, their exclusive prefix (tile_start), counters and
@@ -82,21 +83,29 @@ static __global__ void __launch_bounds__(kSetupThreads) batched_setup_kernel(Bat
     a.ctl[0] = 0;
     a.ctl[1] = 0;
   }
-  // tile -> instance map, one wavefront per instance so that the stores of
-  // an instance's tiles are coalesced (the workgroup's own tile_start writes
-  // are visible after the barrier)
-  // Each wavefront takes 64 consecutive instances, reads their tile ranges
-  // with one coalesced load and walks them with lane broadcasts.
+  // Per-tile records, written once here so that a work item finds its keys
+  // with one read instead of a chain of dependent ones (the workgroup's own
+  // tile_start writes are visible after the barrier).  Each wavefront takes
+  // 64 consecutive instances, reads their tile ranges and segment starts
+  // with coalesced loads and walks them with lane broadcasts; the records of
+  // one instance are stored by consecutive lanes.
   __syncthreads();
   for (uint32_t base = w * kWave; base < a.num; base += kSetupThreads) {
     const uint32_t i = base + lane;
     const uint32_t t0 = i < a.num ? a.tile_start[i] : 0u;
     const uint32_t t1 = i < a.num ? a.tile_start[i + 1] : 0u;
+    const uint32_t k0 = i < a.num ? (uint32_t)a.seg[i] : 0u;
+    const uint32_t k1 = i < a.num ? (uint32_t)a.seg[i + 1] : 0u;
     const uint32_t cnt = min((uint32_t)kWave, a.num - base);
     for (uint32_t j = 0; j < cnt; ++j) {
       const uint32_t s0 = __builtin_amdgcn_readlane(t0, j);
       const uint32_t s1 = __builtin_amdgcn_readlane(t1, j);
-      for (uint32_t t = s0 + lane; t < s1; t += kWave) a.tile_inst[t] = base + j;
+      const uint32_t f0 = __builtin_amdgcn_readlane(k0, j);
+      const uint32_t f1 = __builtin_amdgcn_readlane(k1, j);
+      for (uint32_t t = s0 + lane; t < s1; t += kWave) {
+        const uint32_t first = f0 + (t - s0) * a.tile;
+        a.tile_info[t] = make_uint4(first, min(a.tile, f1 - first), base + j, t - s0);
+      }
     }
   }
 }
@@ -133,6 +142,7 @@ __global__ void __launch_bounds__(WPB* kWave) batched_kernel(BatchedArgs a) {
   constexpr int MB = Owned<BITS>::value;
   constexpr bool TABLES = (Kind == kSplitters || Kind == kLearned);
   __shared__ uint32_t s_tables[TABLES ? (sizeof(BucketLds) + 3) / 4 : 1];
+  // counter rows of the pre-scan's histogram and of the post-scan tiles
   __shared__ uint32_t s_cnt[WPB * kCntStride];
   __shared__ uint32_t s_run[kMaxBuckets];
   __shared__ uint32_t s_delta[kMaxBuckets];
@@ -141,6 +151,15 @@ __global__ void __launch_bounds__(WPB* kWave) batched_kernel(BatchedArgs a) {
   __shared__ uint32_t s_vals[KV ? T : 1];
   __shared__ uint32_t s_tmp[WPB];
   __shared__ uint32_t s_next, s_flag;
+  __shared__ uint4 s_info[kMaxClaim];   // records of the claim's items
+  __shared__ uint32_t s_tiles[kMaxClaim];  // H row length of each item's instance
+  // pre-scan up to 64 buckets: one counter per (bucket, lane), shared by the
+  // workgroup's wavefronts (as the multisplit pre-scan's lane counters);
+  // zero between tiles
+  constexpr bool LANES = BITS <= 6;
+  __shared__ uint32_t s_lane[LANES ? kWave * kWave : 1];
+  if (LANES)
+    for (uint32_t i = threadIdx.x; i < kWave * kWave; i += WPB * kWave) s_lane[i] = 0u;
 
   BucketLds* tables = reinterpret_cast<BucketLds*>(s_tables);
   if (TABLES) stage_bucket_tables<Kind>(a.bp, tables);
@@ -167,9 +186,37 @@ __global__ void __launch_bounds__(WPB* kWave) batched_kernel(BatchedArgs a) {
     if (tid == 0)
       s_next = __hip_atomic_fetch_add(a.ctl, a.claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const uint32_t last = min(items, first + a.claim);
+    // the claim's tile records and H row lengths, one lane per item
+    if (tid < last - first) {
+      const uint32_t it = first + tid;
+      const uint32_t tg = it < P ? it : it - P;
+      const uint4 r = a.tile_info[tg];
+      s_info[tid] = r;
+      s_tiles[tid] = a.tile_start[r.z + 1] - (tg - r.w);
+    }
+    __syncthreads();
 
+    // Keys of work item `it` (a global tile index below P for a pre-scan
+    // item, P + tile for a post-scan item).  Lanes past the tile's end read
+    // the tile's first element, which exists, and are masked out later.
+    uint32_t k[NW], v[NW];
+    auto load_item = [&](uint32_t it, auto vals_tag) {
+      constexpr bool with_vals = decltype(vals_tag)::value;
+      const uint4 r = s_info[it - first];
+      const uint32_t tcount = r.y;
+      const uint32_t tb = r.x;
+      const uint32_t* pk = a.keys_in + tb + wbase + lane;
+      const uint32_t* pv = a.vals_in + tb + wbase + lane;
+#pragma unroll
+      for (int j = 0; j < NW; ++j) {
+        const bool valid = wbase + (uint32_t)(j * kWave) + lane < tcount;
+        k[j] = __builtin_nontemporal_load(valid ? pk + j * kWave : a.keys_in + tb);
+        if (KV && with_vals) v[j] = __builtin_nontemporal_load(valid ? pv + j * kWave : a.vals_in + tb);
+      }
+    };
     // ---- pre-scan items of this claim: one column of H per tile; the
     // columns of one instance are published together (one release) ----
+    const uint32_t pre_end = min(last, P);
     uint32_t pub_inst = 0xFFFFFFFFu, pub_count = 0;
     auto publish = [&]() {
       __syncthreads();
@@ -196,41 +243,19 @@ __global__ void __launch_bounds__(WPB* kWave) batched_kernel(BatchedArgs a) {
       }
       __syncthreads();
     };
-    // Keys of work item `it` (a global tile index below P for a pre-scan
-    // item, P + tile for a post-scan item).  Lanes past the tile's end read
-    // the tile's first element, which exists, and are masked out later.
-    uint32_t k[NW], v[NW];
-    auto load_item = [&](uint32_t it, auto vals_tag) {
-      constexpr bool with_vals = decltype(vals_tag)::value;
-      const uint32_t tg = it < P ? it : it - P;
-      const uint32_t i = a.tile_inst[tg];
-      const uint32_t t = tg - a.tile_start[i];
-      const uint32_t s0 = (uint32_t)a.seg[i];
-      const uint32_t tcount = min((uint32_t)T, (uint32_t)(a.seg[i + 1] - s0) - t * T);
-      const uint32_t tb = s0 + t * T;
-      const uint32_t* pk = a.keys_in + tb + wbase + lane;
-      const uint32_t* pv = a.vals_in + tb + wbase + lane;
-#pragma unroll
-      for (int j = 0; j < NW; ++j) {
-        const bool valid = wbase + (uint32_t)(j * kWave) + lane < tcount;
-        k[j] = __builtin_nontemporal_load(valid ? pk + j * kWave : a.keys_in + tb);
-        if (KV && with_vals) v[j] = __builtin_nontemporal_load(valid ? pv + j * kWave : a.vals_in + tb);
-      }
-    };
-    const uint32_t pre_end = min(last, P);
     if (first < pre_end) load_item(first, std::false_type{});
     for (uint32_t it = first; it < pre_end; ++it) {
-      const uint32_t i = a.tile_inst[it];
+      const uint4 r = s_info[it - first];
+      const uint32_t i = r.z;
       if (i != pub_inst) {
         if (pub_count) publish();
         pub_inst = i;
         pub_count = 0;
       }
-      const uint32_t t = it - a.tile_start[i];
-      const uint32_t tiles = a.tile_start[i + 1] - a.tile_start[i];
-      const uint32_t n_i = (uint32_t)(a.seg[i + 1] - a.seg[i]);
-      const uint32_t tcount = min((uint32_t)T, n_i - t * T);
-      uint32_t* Hi = a.H + (size_t)m * a.tile_start[i];
+      const uint32_t t = r.w;
+      const uint32_t tiles = s_tiles[it - first];
+      const uint32_t tcount = r.y;
+      uint32_t* Hi = a.H + (size_t)m * (it - t);
       uint32_t cnt[MB];
 #pragma unroll
       for (int q = 0; q < MB; ++q) cnt[q] = 0;
@@ -242,26 +267,48 @@ __global__ void __launch_bounds__(WPB* kWave) batched_kernel(BatchedArgs a) {
         const bool valid = wbase + (uint32_t)(j * kWave) + lane < tcount;
         bk[j] = valid ? bf_pre(k[j]) : 0u;
       }
-      if (it + 1 < P)
+      // (only items of this claim: their records are the ones staged)
+      if (it + 1 < pre_end)
         load_item(it + 1, std::false_type{});
       else if (it + 1 < last)
         load_item(it + 1, std::true_type{});  // the claim's first post-scan item
+      if constexpr (LANES) {
+        // every element adds 1 to its lane's counter of its bucket: the 64
+        // lanes of an instruction hit 64 distinct counters
 #pragma unroll
-      for (int j = 0; j < NW; ++j) {
-        const bool valid = wbase + (uint32_t)(j * kWave) + lane < tcount;
-        window_histogram<BITS>(bk[j], ballot(valid), ls, cnt);
-      }
+        for (int j = 0; j < NW; ++j) {
+          const bool valid = wbase + (uint32_t)(j * kWave) + lane < tcount;
+          if (valid)
+            __hip_atomic_fetch_add(&s_lane[bk[j] * kWave + lane], 1u, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+        __syncthreads();
+        // bucket b's count is the sum of its 64 lane counters, which are
+        // cleared for the next tile on the way
+        for (uint32_t b = w; b < m; b += WPB) {
+          const uint32_t c = s_lane[b * kWave + lane];
+          s_lane[b * kWave + lane] = 0u;
+          const uint32_t sum = wave_inclusive_scan(c, lane);
+          if (lane == kWave - 1) Hi[b * tiles + t] = sum;
+        }
+      } else {
 #pragma unroll
-      for (int q = 0; q < MB; ++q) {
-        const uint32_t b = lane + kWave * q;
-        if (b < m) s_cnt[w * kCntStride + b] = cnt[q];
-      }
-      __syncthreads();
-      for (uint32_t b = tid; b < m; b += WPB * kWave) {
-        uint32_t s = 0;
+        for (int j = 0; j < NW; ++j) {
+          const bool valid = wbase + (uint32_t)(j * kWave) + lane < tcount;
+          window_histogram<BITS>(bk[j], ballot(valid), ls, cnt);
+        }
 #pragma unroll
-        for (int ww = 0; ww < WPB; ++ww) s += s_cnt[ww * kCntStride + b];
-        Hi[b * tiles + t] = s;
+        for (int q = 0; q < MB; ++q) {
+          const uint32_t b = lane + kWave * q;
+          if (b < m) s_cnt[w * kCntStride + b] = cnt[q];
+        }
+        __syncthreads();
+        for (uint32_t b = tid; b < m; b += WPB * kWave) {
+          uint32_t s = 0;
+#pragma unroll
+          for (int ww = 0; ww < WPB; ++ww) s += s_cnt[ww * kCntStride + b];
+          Hi[b * tiles + t] = s;
+        }
       }
       __syncthreads();
       ++pub_count;
@@ -277,7 +324,8 @@ __global__ void __launch_bounds__(WPB* kWave) batched_kernel(BatchedArgs a) {
     if (post_first < last && first >= P) load_item(post_first, std::true_type{});
     for (uint32_t it = post_first; it < last; ++it) {
       const uint32_t tg = it - P;
-      const uint32_t i = a.tile_inst[tg];
+      const uint4 r = s_info[it - first];
+      const uint32_t i = r.z;
       if (i != seen) {
         if (tid == 0) {
           uint32_t ok = 1, polls = 0;
@@ -299,12 +347,11 @@ __global__ void __launch_bounds__(WPB* kWave) batched_kernel(BatchedArgs a) {
           continue;  // instance not published in time: tile skipped, status set
         }
       }
-      const uint32_t t = tg - a.tile_start[i];
-      const uint32_t tiles = a.tile_start[i + 1] - a.tile_start[i];
-      const uint32_t s0 = (uint32_t)a.seg[i];
-      const uint32_t n_i = (uint32_t)(a.seg[i + 1] - s0);
-      const uint32_t tcount = min((uint32_t)T, n_i - t * T);
-      const uint32_t* Hi = a.H + (size_t)m * a.tile_start[i];
+      const uint32_t t = r.w;
+      const uint32_t tiles = s_tiles[it - first];
+      const uint32_t s0 = r.x - t * (uint32_t)T;  // the instance's first key
+      const uint32_t tcount = r.y;
+      const uint32_t* Hi = a.H + (size_t)m * (tg - t);
       const TileBufs<KV> tb{s_reorder, s_vals, s_cnt, s_run, s_delta, s_tmp, a.keys_out,
                             a.vals_out};
       // the next item's loads go out once this tile sits in LDS

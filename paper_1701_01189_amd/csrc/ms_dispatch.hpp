@@ -154,7 +154,8 @@ hipError_t post_dispatch(const PostArgs& a, int bits) {
 
 // Batched: shapes (waves per block, windows) with an instantiated kernel.
 inline bool batched_shape_supported(int wpb, int nw) {
-  return wpb == 8 && (nw == 8 || nw == 4);
+  return (wpb == 8 && (nw == 8 || nw == 4)) || (wpb == 4 && (nw == 16 || nw == 8)) ||
+         (wpb == 16 && (nw == 4 || nw == 8));
 }
 
 template <int Kind, int BITS, bool KV, int WPB, int NW>
@@ -178,6 +179,14 @@ hipError_t batched_shape(const BatchedArgs& a, bool kv, int wpb, int nw, hipStre
     return kv ? batched_launch<Kind, BITS, true, 8, 8>(a, st) : batched_launch<Kind, BITS, false, 8, 8>(a, st);
   if (wpb == 8 && nw == 4)
     return kv ? batched_launch<Kind, BITS, true, 8, 4>(a, st) : batched_launch<Kind, BITS, false, 8, 4>(a, st);
+  if (wpb == 4 && nw == 16)
+    return kv ? batched_launch<Kind, BITS, true, 4, 16>(a, st) : batched_launch<Kind, BITS, false, 4, 16>(a, st);
+  if (wpb == 4 && nw == 8)
+    return kv ? batched_launch<Kind, BITS, true, 4, 8>(a, st) : batched_launch<Kind, BITS, false, 4, 8>(a, st);
+  if (wpb == 16 && nw == 4)
+    return kv ? batched_launch<Kind, BITS, true, 16, 4>(a, st) : batched_launch<Kind, BITS, false, 16, 4>(a, st);
+  if (wpb == 16 && nw == 8)
+    return kv ? batched_launch<Kind, BITS, true, 16, 8>(a, st) : batched_launch<Kind, BITS, false, 16, 8>(a, st);
   return hipErrorInvalidValue;
 }
 

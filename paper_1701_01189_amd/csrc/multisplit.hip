@@ -290,7 +290,7 @@ int resolve_batch_shape(const ms_options* opt, BatchShape* b) {
     b->never_ready = opt->test_flags & 1u;
     if (opt->reorder != MS_REORDER_AUTO && opt->reorder != MS_REORDER_BLOCK) return MS_ERR_UNSUPPORTED;
   }
-  if (b->claim > 64) return MS_ERR_INVALID_ARG;
+  if (b->claim > (uint32_t)ms::kMaxClaim) return MS_ERR_INVALID_ARG;
   if (!ms::batched_shape_supported(b->wpb, b->nw)) return MS_ERR_UNSUPPORTED;
   b->tile = (uint32_t)(b->wpb * b->nw * ms::kWave);
   return MS_OK;
@@ -299,14 +299,14 @@ int resolve_batch_shape(const ms_options* opt, BatchShape* b) {
 struct BatchWorkspace {
   uint32_t* ctl;
   uint32_t* tile_start;
-  uint32_t* tile_inst;
+  uint4* tile_info;
   uint32_t* done;
   uint32_t* ready;
   uint32_t* offsets;
   uint32_t* H;
 };
 
-// [ctl: 2 words | tile_start: num+1 | tile_inst: tiles | done: num |
+// [ctl: 2 words | tile_start: num+1 | tile_info: 4 words per tile | done: num |
 //  ready: num | spare offsets: num*(m+1) | H: m x tiles words], with
 // tiles = total/tile + num bounding the number of tiles.
 size_t batch_layout(size_t total, uint32_t m, uint32_t num, const BatchShape& bs,
@@ -320,7 +320,7 @@ size_t batch_layout(size_t total, uint32_t m, uint32_t num, const BatchShape& bs
   size_t o_ctl = take(64);
   size_t o_ts = take(((size_t)num + 1) * 4);
   size_t tiles = (total + bs.tile - 1) / bs.tile + num;
-  size_t o_ti = take(tiles * 4);
+  size_t o_ti = take(tiles * 16);
   size_t o_done = take((size_t)num * 4);
   size_t o_ready = take((size_t)num * 4);
   size_t o_off = take((size_t)num * (m + 1) * 4);
@@ -328,7 +328,7 @@ size_t batch_layout(size_t total, uint32_t m, uint32_t num, const BatchShape& bs
   if (w && base) {
     w->ctl = (uint32_t*)(base + o_ctl);
     w->tile_start = (uint32_t*)(base + o_ts);
-    w->tile_inst = (uint32_t*)(base + o_ti);
+    w->tile_info = (uint4*)(base + o_ti);
     w->done = (uint32_t*)(base + o_done);
     w->ready = (uint32_t*)(base + o_ready);
     w->offsets = (uint32_t*)(base + o_off);
@@ -581,7 +581,9 @@ size_t ms_workspace_size(int op, size_t n, uint32_t m, uint32_t num_inst, const 
   }
   const bool kv_op = op == MS_OP_PAIRS || op == MS_OP_RADIX_SORT_PAIRS;
   Shape s;  // radix passes use shift/mask buckets
-  if (resolve_shape(opt, n, m, MS_BUCKET_SHIFT_MASK, kv_op, &s) != MS_OK) return 0;
+  const bool multisplit_op = op != MS_OP_BATCHED && op != MS_OP_LEARNED_FIT;
+  if (multisplit_op && resolve_shape(opt, n, m, MS_BUCKET_SHIFT_MASK, kv_op, &s) != MS_OK)
+    return 0;
   switch (op) {
     case MS_OP_KEYS:
     case MS_OP_PAIRS:
@@ -800,7 +802,7 @@ ms_status ms_batched(const uint32_t* d_keys_in, const uint32_t* d_vals_in, uint3
   a.m = m;
   a.offsets = d_offsets ? d_offsets : w.offsets;
   a.tile_start = w.tile_start;
-  a.tile_inst = w.tile_inst;
+  a.tile_info = w.tile_info;
   a.H = w.H;
   a.done = w.done;
   a.ready = w.ready;
@@ -874,10 +876,12 @@ ms_status ms_autotune(int op, const uint32_t* d_keys_in, const uint32_t* d_vals_
                                 {MS_REORDER_BLOCK, 16, 8, 0}, {MS_REORDER_BLOCK, 16, 16, 0},
                                 {MS_REORDER_WAVE, 8, 8, 0},   {MS_REORDER_WAVE, 4, 16, 0},
                                 {MS_REORDER_NONE, 8, 8, 0}};
-  static const Cand kBatch[] = {{MS_REORDER_BLOCK, 8, 8, 1},  {MS_REORDER_BLOCK, 8, 8, 4},
-                                {MS_REORDER_BLOCK, 8, 8, 8},  {MS_REORDER_BLOCK, 8, 8, 16},
-                                {MS_REORDER_BLOCK, 8, 8, 32}, {MS_REORDER_BLOCK, 8, 4, 4},
-                                {MS_REORDER_BLOCK, 8, 4, 16}, {MS_REORDER_BLOCK, 8, 4, 32}};
+  static const Cand kBatch[] = {{MS_REORDER_BLOCK, 8, 8, 4},   {MS_REORDER_BLOCK, 8, 8, 16},
+                                {MS_REORDER_BLOCK, 8, 8, 32},  {MS_REORDER_BLOCK, 8, 4, 4},
+                                {MS_REORDER_BLOCK, 8, 4, 16},  {MS_REORDER_BLOCK, 8, 4, 32},
+                                {MS_REORDER_BLOCK, 4, 16, 16}, {MS_REORDER_BLOCK, 4, 8, 16},
+                                {MS_REORDER_BLOCK, 16, 4, 16}, {MS_REORDER_BLOCK, 16, 4, 32},
+                                {MS_REORDER_BLOCK, 16, 8, 16}, {MS_REORDER_BLOCK, 16, 8, 32}};
   const bool batched = op == MS_OP_BATCHED;
   const bool radix = op == MS_OP_RADIX_SORT || op == MS_OP_RADIX_SORT_PAIRS;
   if (!batched && !radix && op != MS_OP_KEYS && op != MS_OP_PAIRS) return MS_ERR_INVALID_ARG;
