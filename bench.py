@@ -55,6 +55,7 @@ BYTES_PER_PAIR = 20
 POST_BYTES_PER_KEY = 8
 POST_BYTES_PER_PAIR = 16
 GATE_FRAC = 0.60  # key-only, m <= 32: at least 60 % of the HBM peak, whole call
+GRAPH_CALLS = 10  # calls captured per HIP graph when replays are timed
 
 
 def progress(msg):
@@ -326,18 +327,23 @@ def time_calls(step, K, warmup, stages=True, graph=False):
             step(None)
         stream.wait_stream(side)
         torch.cuda.synchronize()
+        # GRAPH_CALLS calls per graph: a captured loop of calls, as a serving
+        # loop would replay it (one call per graph measures the runtime's
+        # cost of launching a graph, tens of microseconds, instead)
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g):
-            step(None)
+            for _ in range(GRAPH_CALLS):
+                step(None)
         for _ in range(warmup):
             g.replay()
         torch.cuda.synchronize()
+        reps = max(1, K // GRAPH_CALLS)
         t0.record(stream)
-        for _ in range(K):
+        for _ in range(reps):
             g.replay()
         t1.record(stream)
         torch.cuda.synchronize()
-        out["graph_ms"] = t0.elapsed_time(t1) / K
+        out["graph_ms"] = t0.elapsed_time(t1) / (reps * GRAPH_CALLS)
         del g
     return out
 
@@ -391,7 +397,8 @@ def multisplit_row(args, name, dk, dv, m, fn, shape=(0, 0, 0), graph=False, cpu=
         "workload": name, "n": n, "m": mm, "kv": kv,
         "value": round(value, 3), "unit": "Gpairs/s" if kv else "Gkeys/s",
         "ms_per_call": round(call_ms, 5),
-        "timing": "hipgraph replays" if graph else "back-to-back eager calls",
+        "timing": ("hipgraph replays, %d calls per graph" % GRAPH_CALLS) if graph else
+                  "back-to-back eager calls",
         "stage_ms": {"prescan": round(t["stage"][0], 5), "scan": round(t["stage"][1], 5),
                      "postscan": round(post_ms, 5)},
         "roofline": roofline(kern, name, n * (POST_BYTES_PER_PAIR if kv else POST_BYTES_PER_KEY),
@@ -637,7 +644,8 @@ def row_config4(args, dev):
     row = {
         "workload": "batched_4096_m64", "instances": num, "n": total, "m": m, "kv": True,
         "value": round(total / (call_ms * 1e-3) / 1e9, 3), "unit": "Gpairs/s",
-        "ms_per_call": round(call_ms, 5), "timing": "hipgraph replays",
+        "ms_per_call": round(call_ms, 5),
+        "timing": "hipgraph replays, %d calls per graph" % GRAPH_CALLS,
         "eager_ms_per_call": round(eager_ms, 5),
         "status": status,
         "tuning": {"reorder": opt.reorder, "waves_per_block": opt.waves_per_block,
@@ -883,7 +891,7 @@ def bench_hist(args, kind, n, m, shift, seed, dev):
         "config": {"workload": args.workload, "n": n, "m": m,
                    "bins": "range (m-1 random splitters)" if spl is not None else
                            "even (k >> %d)" % shift, "seed": seed, **base},
-        "timing": "hipgraph replays",
+        "timing": "hipgraph replays, %d calls per graph" % GRAPH_CALLS,
         "eager_value": round(n / (t["ms"] * 1e-3) / 1e9, 3),
         "stage_ms": {"prescan": round(st[0], 5), "reduce": round(st[1], 5)},
         "roofline": roofline("prescan", args.workload, 4.0 * n, st[0]),

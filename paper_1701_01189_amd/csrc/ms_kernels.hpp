@@ -23,6 +23,8 @@ struct Plan {
   uint32_t L0;        // chunks = columns of H
   uint32_t chunk;     // elements per chunk (multiple of the tile size)
   uint32_t tile;      // elements per tile
+  uint32_t h_raw;     // 1: H is not scanned; every post-scan workgroup reads it
+                      // whole (block-level reordering, at most 64 buckets)
 };
 
 // ---------------------------------------------------------------------------
@@ -242,14 +244,44 @@ postscan_kernel(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict
   // keeps bucket b's position in lane b.
   uint32_t run = 0;
   if (SMALL) {
-    const uint32_t tot = lane < m ? totals[lane] : 0u;
+    uint32_t tot, gpos = 0;  // gpos: G[b][c] (or G[b][c + 1] for reversed tiles)
+    if (GPB == 1 && plan.h_raw) {
+      // Small H (the scan kernel is not launched): every workgroup sums it
+      // itself.  Wavefront w takes buckets w, w + WPB, ...: its lanes stride
+      // over the bucket's row, and the row total and the sum of the columns
+      // before the group's position go to LDS (s_cnt is free until the
+      // tiles start).
+      const uint32_t cend = REV ? c + 1 : c;  // columns summed into gpos
+      for (uint32_t b = w; b < m; b += WPB) {
+        uint32_t all = 0, before = 0;
+        for (uint32_t cc = lane; cc < plan.L0; cc += kWave) {
+          const uint32_t h = G[b * plan.L0 + cc];
+          all += h;
+          before += cc < cend ? h : 0u;
+        }
+        all = wave_inclusive_scan(all, lane);
+        before = wave_inclusive_scan(before, lane);
+        if (lane == kWave - 1) {
+          s_cnt[b] = all;
+          s_cnt[kWave + b] = before;
+        }
+      }
+      __syncthreads();
+      tot = lane < m ? s_cnt[lane] : 0u;
+      gpos = lane < m ? s_cnt[kWave + lane] : 0u;
+      __syncthreads();  // s_cnt is reused by the tiles
+    } else {
+      tot = lane < m ? totals[lane] : 0u;
+    }
     const uint32_t bb = wave_inclusive_scan(tot, lane) - tot;
     if (blockIdx.x == 0 && w == 0) {
       if (lane < m) offsets[lane] = bb;
       if (lane == 0) offsets[m] = plan.n;
     }
     if (c < plan.L0 && lane < m) {
-      if (REV)
+      if (GPB == 1 && plan.h_raw)
+        run = bb + gpos;
+      else if (REV)
         run = bb + (c + 1 < plan.L0 ? G[lane * plan.L0 + c + 1] : tot);
       else
         run = bb + G[lane * plan.L0 + c];

@@ -160,6 +160,7 @@ Plan make_plan(size_t n, uint32_t m, const Shape& s, uint32_t groups) {
   if (L0 == 0) L0 = 1;
   p.L0 = (uint32_t)L0;
   p.chunk = (uint32_t)(tpc * p.tile);
+  p.h_raw = 0;
   return p;
 }
 
@@ -373,6 +374,8 @@ uint32_t resident_groups(int kind, int bits, bool kv, const Shape& s) {
   return device_cus() * (uint32_t)occ * (uint32_t)(s.wpb / wpg);
 }
 
+constexpr size_t kRawH = 4096;
+
 // The three stages for one multisplit on already validated arguments.
 ms_status run_multisplit(const uint32_t* ki, const uint32_t* vi, uint32_t* ko, uint32_t* vo,
                          uint32_t* offsets, size_t n, uint32_t m, const ms_bucket_fn* fn,
@@ -391,9 +394,15 @@ ms_status run_multisplit(const uint32_t* ki, const uint32_t* vi, uint32_t* ko, u
   ms::PreArgs pa{ki, p, bp, w.H, s.mode, s.hist, st};
   if (pre_by_kind(fn->kind, pa, bits) != hipSuccess) return MS_ERR_HIP;
   if (record(opt, 1, st) != hipSuccess) return MS_ERR_HIP;
-  hipLaunchKernelGGL(ms::scan_rows_kernel, dim3(m), dim3(ms::kScanThreads), 0, st, w.H, p.L0,
-                     w.totals);
-  if (hipGetLastError() != hipSuccess) return MS_ERR_HIP;
+  // A small H (at most kRawH words, block-level reordering, up to 64
+  // buckets) is summed by every post-scan workgroup itself: one launch less
+  // for inputs that take microseconds.
+  p.h_raw = (s.mode == ms::kBlock && m <= 64 && (size_t)m * p.L0 <= kRawH) ? 1u : 0u;
+  if (!p.h_raw) {
+    hipLaunchKernelGGL(ms::scan_rows_kernel, dim3(m), dim3(ms::kScanThreads), 0, st, w.H, p.L0,
+                       w.totals);
+    if (hipGetLastError() != hipSuccess) return MS_ERR_HIP;
+  }
   if (record(opt, 2, st) != hipSuccess) return MS_ERR_HIP;
   // offsets are written by workgroup 0 of the post-scan; a NULL offsets
   // pointer is redirected to the spare words after the bucket totals.
