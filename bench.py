@@ -83,6 +83,8 @@ def parse():
     ap.add_argument("--items", type=int, default=0)
     ap.add_argument("--chunks", type=int, default=0)
     ap.add_argument("--claim", type=int, default=0, help="batched: work items per queue claim")
+    ap.add_argument("--keep-ids", type=int, default=1,
+                    help="range buckets: the pre-scan keeps bucket ids for the post-scan")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="oracle time budget of the headline (or single workload)")
@@ -352,7 +354,7 @@ def time_calls(step, K, warmup, stages=True, graph=False):
 # multisplit rows
 # ---------------------------------------------------------------------------
 def multisplit_row(args, name, dk, dv, m, fn, shape=(0, 0, 0), graph=False, cpu=None,
-                   ceiling=None, radix_bits=0, tune=False):
+                   ceiling=None, radix_bits=0, tune=False, keep_ids=0):
     """One multisplit (or radix sort when radix_bits) workload on resident
     device inputs.  With tune, the shape comes from the autotuner through
     its cache.  Returns the row dict."""
@@ -370,10 +372,11 @@ def multisplit_row(args, name, dk, dv, m, fn, shape=(0, 0, 0), graph=False, cpu=
           (ms.OP_PAIRS if kv else ms.OP_KEYS))
     tuned = None
     if tune and shape == (0, 0, 0):
-        topt, tuned = tuning.tuned_options(op, dk, dv, radix_bits if radix_bits else m, fn=fn)
+        topt, tuned = tuning.tuned_options(op, dk, dv, radix_bits if radix_bits else m, fn=fn,
+                                           keep_bucket_ids=keep_ids)
         shape = (topt.reorder, topt.waves_per_block, topt.items_per_lane)
     base = dict(reorder=shape[0], waves_per_block=shape[1], items_per_lane=shape[2],
-                max_chunks=args.chunks)
+                max_chunks=args.chunks, keep_bucket_ids=keep_ids)
     ws = torch.empty(max(256, ms.workspace_size(op, n, mm, 0, ms.Options(**base))),
                      dtype=torch.uint8, device=dk.device)
     opt_plain = ms.Options(**base)
@@ -413,6 +416,9 @@ def multisplit_row(args, name, dk, dv, m, fn, shape=(0, 0, 0), graph=False, cpu=
     if shape != (0, 0, 0):
         row["shape"] = {"reorder": ["auto", "block", "wave", "none"][shape[0]],
                         "waves_per_block": shape[1], "windows_per_wave": shape[2]}
+    if keep_ids:
+        row["kept_bucket_ids"] = True
+        row["bytes_per_unit"] = call_bytes(kv) + 2  # + 1 B id written, 1 B read
     if tuned is not None:
         row["tuner"] = tuned
     if cpu is not None and not args.no_cpu_baseline:
@@ -575,6 +581,7 @@ def row_config3(args, dev, ceiling):
                      ("binary_search", ms.BucketFn.splitter(ds))):
         res[name] = multisplit_row(
             args, "range_2e27_m256_" + name, dk, None, m, fn, ceiling=ceiling, tune=True,
+            keep_ids=args.keep_ids, shape=(args.reorder, args.waves, args.items),
             cpu=(lambda: cpu_baseline("range", keys, None, m, 0, args.row_cpu_seconds, 1 << 22,
                                       splitters=spl)) if name == "learned" else None)
     miss = torch.zeros(1, dtype=torch.int64, device=dev)

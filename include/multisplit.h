@@ -121,11 +121,16 @@ enum {
  * Optional tuning and instrumentation; pass NULL for defaults.  Every field
  * may be 0 (= choose automatically).  Tuning never changes results.
  *   reorder          MS_REORDER_*.
- *   waves_per_block  4 or 8 wavefronts of 64 lanes per workgroup.
+ *   waves_per_block  4, 8 or 16 wavefronts of 64 lanes per workgroup.
  *   items_per_lane   windows of 64 elements each wavefront ranks per tile
- *                    (the paper's N_window): 4, 8 or 16.
+ *                    (the paper's N_window): 4, 8 or 16.  Block-level shapes
+ *                    (waves x windows): 8x8, 8x4, 4x8, 4x16, 16x8, 16x16
+ *                    (16x16 only where its buffers fit in LDS); wave level
+ *                    8x8, 4x16; no reordering 8x8.  ms_batched: 8x8, 8x4,
+ *                    4x16, 4x8, 16x4, 16x8.
  *   max_chunks       upper bound on the number of subproblems L0 (columns
- *                    of H); 0 = enough to fill every compute unit once.
+ *                    of H, at most 4096); 0 = a whole multiple of the
+ *                    post-scan workgroups resident at once, at least 1024.
  *   stage_events     if non-NULL, four hipEvent_t (as void*) that are
  *                    recorded on `stream` before the pre-scan, before the
  *                    scan, before the post-scan and after the post-scan.
@@ -140,6 +145,14 @@ enum {
  *                    bit 1: ms_autotune treats its first candidate as
  *                    failed (exercises the skip of failing candidates).
  *   prescan          MS_PRESCAN_*: how the pre-scan counts buckets.
+ *   keep_bucket_ids  SPLITTERS and LEARNED buckets, ms_keys / ms_pairs up to
+ *                    256 buckets: 1 = the pre-scan stores every key's bucket
+ *                    id (one byte) in the workspace and the post-scan reads
+ *                    it instead of identifying the bucket again (2 more
+ *                    bytes of traffic per key, one bucket search less);
+ *                    ms_workspace_size then counts n more bytes.  With
+ *                    LEARNED buckets d_mispredicts is then counted by the
+ *                    pre-scan.  Other kinds and operations ignore it.
  */
 typedef struct {
   int32_t reorder;
@@ -152,6 +165,7 @@ typedef struct {
   uint32_t spin_limit;
   uint32_t test_flags;
   int32_t prescan;
+  int32_t keep_bucket_ids;
 } ms_options;
 
 /*

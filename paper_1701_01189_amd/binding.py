@@ -49,7 +49,8 @@ class OptionsC(ctypes.Structure):
                 ("items_per_lane", ctypes.c_int32), ("max_chunks", ctypes.c_int32),
                 ("stage_events", ctypes.c_void_p), ("d_mispredicts", ctypes.c_void_p),
                 ("batch_claim", ctypes.c_uint32), ("spin_limit", ctypes.c_uint32),
-                ("test_flags", ctypes.c_uint32), ("prescan", ctypes.c_int32)]
+                ("test_flags", ctypes.c_uint32), ("prescan", ctypes.c_int32),
+                ("keep_bucket_ids", ctypes.c_int32)]
 
 
 _lib = None
@@ -176,9 +177,9 @@ class Options:
 
     def __init__(self, reorder=0, waves_per_block=0, items_per_lane=0, max_chunks=0,
                  stage_events=None, mispredicts=None, batch_claim=0, spin_limit=0,
-                 test_flags=0, prescan=0):
+                 test_flags=0, prescan=0, keep_bucket_ids=0):
         self.reorder, self.waves_per_block = reorder, waves_per_block
-        self.prescan = prescan
+        self.prescan, self.keep_bucket_ids = prescan, keep_bucket_ids
         self.items_per_lane, self.max_chunks = items_per_lane, max_chunks
         self.batch_claim, self.spin_limit, self.test_flags = batch_claim, spin_limit, test_flags
         self.stage_events = stage_events   # list of 4 torch.cuda.Event or None
@@ -192,7 +193,7 @@ class Options:
             ev = ctypes.cast(self._ev, ctypes.c_void_p)
         return OptionsC(self.reorder, self.waves_per_block, self.items_per_lane,
                         self.max_chunks, ev, _ptr(self.mispredicts), self.batch_claim,
-                        self.spin_limit, self.test_flags, self.prescan)
+                        self.spin_limit, self.test_flags, self.prescan, self.keep_bucket_ids)
 
 
 def _opt(options):
@@ -358,10 +359,11 @@ def autotune(op, keys_in, vals_in, m, fn=None, seg=None, reps=3, base=None, stre
               (4, 16, 2), (8, 8, 3))
     if op == OP_BATCHED:
         shapes = ((8, 8, 1), (8, 4, 1), (4, 16, 1), (4, 8, 1), (16, 4, 1), (16, 8, 1))
+    keep = base.keep_bucket_ids if base is not None else 0
     for wpb, nw, mode in shapes:
         need = max(need, workspace_size(op, n, (1 << m) if radix else m, num,
                                         Options(reorder=mode, waves_per_block=wpb,
-                                                items_per_lane=nw)))
+                                                items_per_lane=nw, keep_bucket_ids=keep)))
     ws = torch.empty(max(need, 256), dtype=torch.uint8, device=keys_in.device)
     best = OptionsC()
     ms_ = ctypes.c_float(0.0)
@@ -376,7 +378,8 @@ def autotune(op, keys_in, vals_in, m, fn=None, seg=None, reps=3, base=None, stre
     opt = Options(reorder=best.reorder, waves_per_block=best.waves_per_block,
                   items_per_lane=best.items_per_lane, max_chunks=best.max_chunks,
                   batch_claim=best.batch_claim, spin_limit=best.spin_limit,
-                  test_flags=best.test_flags, prescan=best.prescan)
+                  test_flags=best.test_flags, prescan=best.prescan,
+                  keep_bucket_ids=best.keep_bucket_ids)
     return opt, float(ms_.value)
 
 

@@ -354,22 +354,27 @@ __global__ void __launch_bounds__(WPB* kWave) batched_kernel(BatchedArgs a) {
       const uint32_t* Hi = a.H + (size_t)m * (tg - t);
       const TileBufs<KV> tb{s_reorder, s_vals, s_cnt, s_run, s_delta, s_tmp, a.keys_out,
                             a.vals_out};
+      const uint32_t idv[NW] = {};  // (bucket ids are computed here)
       // the next item's loads go out once this tile sits in LDS
       auto next = [&] { if (it + 1 < last) load_item(it + 1, std::true_type{}); };
       if constexpr (BITS <= 6) {
         // lane b of every wavefront holds bucket b's output position
         uint32_t run = lane < m ? s0 + Hi[lane * tiles + t] : 0u;
         if (tcount == (uint32_t)T)
-          tile_small<BITS, KV, WPB, NW, true, false>(bf_post, k, v, tb, tcount, w, lane, run, next);
+          tile_small<BITS, KV, WPB, NW, true, false>(bf_post, k, v, idv, false, tb, tcount, w, lane,
+                                                     run, next);
         else
-          tile_small<BITS, KV, WPB, NW, false, false>(bf_post, k, v, tb, tcount, w, lane, run, next);
+          tile_small<BITS, KV, WPB, NW, false, false>(bf_post, k, v, idv, false, tb, tcount, w, lane,
+                                                      run, next);
       } else {
         for (uint32_t b = tid; b < m; b += WPB * kWave) s_run[b] = s0 + Hi[b * tiles + t];
         __syncthreads();
         if (tcount == (uint32_t)T)
-          tile_large<BITS, KV, WPB, NW, true, false>(bf_post, k, v, tb, m, tcount, w, lane, next);
+          tile_large<BITS, KV, WPB, NW, true, false>(bf_post, k, v, idv, false, tb, m, tcount, w,
+                                                     lane, next);
         else
-          tile_large<BITS, KV, WPB, NW, false, false>(bf_post, k, v, tb, m, tcount, w, lane, next);
+          tile_large<BITS, KV, WPB, NW, false, false>(bf_post, k, v, idv, false, tb, m, tcount, w,
+                                                      lane, next);
       }
       __syncthreads();
     }

@@ -18,7 +18,7 @@ constexpr int kMaxBuckets = 256;   // m <= 256
 constexpr int kLeaves = 256;       // learned model leaves
 constexpr int kModelFloats = 2 + 2 * kLeaves;
 
-enum BucketKind { kShiftMask = 0, kDiv = 1, kSplitters = 2, kLearned = 3 };
+enum BucketKind { kShiftMask = 0, kDiv = 1, kSplitters = 2, kLearned = 3, kKeptIds = 4 };
 
 // ---------------------------------------------------------------------------
 // wavefront primitives
@@ -285,6 +285,17 @@ struct Bucket<kLearned, BITS> {
     return c;
   }
   __device__ __forceinline__ uint32_t misses() const { return miss; }
+};
+
+// Post-scan of table-search buckets whose ids the pre-scan kept: every id
+// comes from the kept bytes, so the post-scan carries no table, model or
+// search (fewer registers, no LDS tables).  The key is never looked at.
+template <int BITS>
+struct Bucket<kKeptIds, BITS> {
+  static constexpr bool kCheap = false;
+  __device__ Bucket(const BucketParams&, const BucketLds*) {}
+  __device__ __forceinline__ uint32_t operator()(uint32_t) const { return 0u; }
+  __device__ __forceinline__ uint32_t misses() const { return 0; }
 };
 
 // Stage splitters (padded) and the learned model into LDS.

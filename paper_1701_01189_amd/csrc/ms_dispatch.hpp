@@ -18,6 +18,7 @@ struct PreArgs {
   int mode;
   int hist;  // kHistBallot / kHistLanes (block mode only)
   hipStream_t stream;
+  uint8_t* ids;  // table-search kinds: each key's bucket id is stored here (or NULL)
 };
 
 struct PostArgs {
@@ -34,6 +35,7 @@ struct PostArgs {
   bool kv;
   hipStream_t stream;
   int* occupancy;  // if set: store the kernel's resident workgroups per CU, launch nothing
+  const uint8_t* ids;  // table-search kinds: bucket ids kept by the pre-scan (or NULL)
 };
 
 // Shapes with an instantiated post-scan: (mode, waves per block, windows).
@@ -55,15 +57,15 @@ hipError_t pre_launch(const PreArgs& a) {
   if (a.mode == kBlock && a.hist == kHistLanes) {
     hipLaunchKernelGGL((prescan_kernel<Kind, BITS, kPreWaves, kPreWaves, kHistLanes>),
                        dim3(a.plan.L0), dim3(kPreWaves * kWave), 0, a.stream, a.keys, a.plan,
-                       a.bp, a.H);
+                       a.bp, a.H, a.ids);
   } else if (a.mode == kBlock) {
     hipLaunchKernelGGL((prescan_kernel<Kind, BITS, kPreWaves, kPreWaves, kHistBallot>),
                        dim3(a.plan.L0), dim3(kPreWaves * kWave), 0, a.stream, a.keys, a.plan,
-                       a.bp, a.H);
+                       a.bp, a.H, a.ids);
   } else {
     hipLaunchKernelGGL((prescan_kernel<Kind, BITS, kPreWaves, 1, kHistBallot>),
                        dim3((a.plan.L0 + kPreWaves - 1) / kPreWaves), dim3(kPreWaves * kWave), 0,
-                       a.stream, a.keys, a.plan, a.bp, a.H);
+                       a.stream, a.keys, a.plan, a.bp, a.H, a.ids);
   }
   return hipGetLastError();
 }
@@ -104,7 +106,7 @@ hipError_t post_launch(const PostArgs& a) {
   }
   dim3 grid((a.plan.L0 + GPB - 1) / GPB), block(WPB * kWave);
   hipLaunchKernelGGL(kern, grid, block, 0, a.stream, a.keys_in, a.vals_in, a.keys_out,
-                     a.vals_out, a.G, a.totals, a.offsets, a.plan, a.bp);
+                     a.vals_out, a.G, a.totals, a.offsets, a.plan, a.bp, a.ids);
   return hipGetLastError();
 }
 
@@ -216,6 +218,7 @@ hipError_t post_shift_mask(const PostArgs& a, int bits);
 hipError_t post_div(const PostArgs& a, int bits);
 hipError_t post_splitters(const PostArgs& a, int bits);
 hipError_t post_learned(const PostArgs& a, int bits);
+hipError_t post_kept_ids(const PostArgs& a, int bits);
 hipError_t batched_shift_mask(const BatchedArgs& a, int bits, bool kv, int wpb, int nw, hipStream_t st);
 hipError_t batched_div(const BatchedArgs& a, int bits, bool kv, int wpb, int nw, hipStream_t st);
 hipError_t batched_splitters(const BatchedArgs& a, int bits, bool kv, int wpb, int nw, hipStream_t st);

@@ -49,7 +49,7 @@ enum Hist { kHistBallot = 0, kHistLanes = 1 };
 template <int Kind, int BITS, int WPB, int WPG, int HIST>
 __global__ void __launch_bounds__(WPB* kWave)
 prescan_kernel(const uint32_t* __restrict__ keys, Plan plan, BucketParams bp,
-               uint32_t* __restrict__ H) {
+               uint32_t* __restrict__ H, uint8_t* __restrict__ ids) {
   static_assert(HIST == kHistBallot || WPG > 1, "lane counters need a shared chunk");
   constexpr int GPB = WPB / WPG;
   constexpr int MB = Owned<BITS>::value;
@@ -96,10 +96,15 @@ prescan_kernel(const uint32_t* __restrict__ keys, Plan plan, BucketParams bp,
 #pragma unroll
       for (int u = 0; u < U; ++u) k[u] = base[gi * BATCH + u * kWave];
     }
+    constexpr bool TABLES = (Kind == kSplitters || Kind == kLearned);
     while (gi < full) {
       uint32_t b[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) b[u] = bf(k[u]);
+      if (TABLES && ids) {  // kept for the post-scan
+#pragma unroll
+        for (int u = 0; u < U; ++u) ids[c0 + gi * BATCH + u * kWave + lane] = (uint8_t)b[u];
+      }
       const uint32_t next = gi + WPG;
       if (next < full) {
 #pragma unroll
@@ -123,6 +128,7 @@ prescan_kernel(const uint32_t* __restrict__ keys, Plan plan, BucketParams bp,
       for (int u = 0; u < U; ++u) {
         const bool valid = (uint32_t)(u * kWave) + lane < rem;
         const uint32_t b = valid ? bf(p[u * kWave]) : 0u;
+        if (TABLES && ids && valid) ids[c0 + full * BATCH + u * kWave + lane] = (uint8_t)b;
         if (LANES) {
           if (valid) lane_count(b, lane);
         } else {
@@ -130,6 +136,13 @@ prescan_kernel(const uint32_t* __restrict__ keys, Plan plan, BucketParams bp,
         }
       }
     }
+  }
+  if (Kind == kLearned && ids && bp.mispredicts) {
+    // the post-scan reads the kept ids: the raw predictions are counted here
+    uint32_t miss = bf.misses();
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) miss += __shfl_xor(miss, d, kWave);
+    if (lane == 0 && miss) atomicAdd(bp.mispredicts, (unsigned long long)miss);
   }
   if (WPG == 1) {
     if (c < plan.L0) {
@@ -194,7 +207,7 @@ constexpr size_t postscan_lds_bytes() {
   constexpr size_t GPB = WPB / WPG, T = (size_t)WPG * NW * kWave;
   constexpr bool REORDER = MODE != kDirect, SMALL = BITS <= 6;
   constexpr bool TABLES = (Kind == kSplitters || Kind == kLearned);
-  constexpr size_t SLOT = reorder_bytes_per_slot<SMALL, !TABLES>();
+  constexpr size_t SLOT = reorder_bytes_per_slot<SMALL, Bucket<Kind, BITS>::kCheap>();
   return (TABLES ? (sizeof(BucketLds) + 3) / 4 * 4 : 4) +
          (size_t)WPB * (SMALL ? kWave : kCntStride) * 4 + (SMALL ? 4 : GPB * kMaxBuckets * 4) +
          ((REORDER && !SMALL) ? GPB * kMaxBuckets * 4 : 4) +
@@ -208,13 +221,15 @@ __global__ void __launch_bounds__(WPB* kWave)
 postscan_kernel(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
                 uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
                 const uint32_t* __restrict__ G, const uint32_t* __restrict__ totals,
-                uint32_t* __restrict__ offsets, Plan plan, BucketParams bp) {
+                uint32_t* __restrict__ offsets, Plan plan, BucketParams bp,
+                const uint8_t* __restrict__ ids) {
   constexpr int WPG = (MODE == kBlock) ? WPB : 1;
   constexpr int GPB = WPB / WPG;
   constexpr int T = WPG * NW * kWave;
   constexpr bool REORDER = (MODE != kDirect);
   constexpr bool SMALL = BITS <= 6;  // one bucket per lane
   constexpr bool TABLES = (Kind == kSplitters || Kind == kLearned);
+  constexpr bool KEPT = Kind == kKeptIds;  // ids always come from the pre-scan's bytes
   constexpr int S = SMALL ? kWave : kCntStride;  // counter row stride
   constexpr bool REV = kReverseTiles && REORDER;
   static_assert(SMALL || WPB * kWave >= kMaxBuckets, "one thread per bucket base");
@@ -223,7 +238,7 @@ postscan_kernel(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict
   __shared__ uint32_t s_cnt[WPB * S];
   __shared__ uint32_t s_run[SMALL ? 1 : GPB * kMaxBuckets];
   __shared__ uint32_t s_delta[(REORDER && !SMALL) ? GPB * kMaxBuckets : 1];
-  constexpr int SLOT = reorder_bytes_per_slot<SMALL, !TABLES>();
+  constexpr int SLOT = reorder_bytes_per_slot<SMALL, Bucket<Kind, BITS>::kCheap>();
   __shared__ uint64_t s_reorder[REORDER ? (GPB * T * SLOT + 7) / 8 : 1];
   __shared__ uint32_t s_vals[(REORDER && KV) ? GPB * T : 1];
   __shared__ uint32_t s_tmp[WPB];
@@ -344,7 +359,10 @@ postscan_kernel(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict
 #pragma unroll
       for (int j = 0; j < NW; ++j) {
         const bool valid = (uint32_t)(j * kWave) + lane < rem;
-        const uint32_t b = valid ? bf(k[j]) : 0u;
+        uint32_t b = 0;
+        if (valid)
+          b = (KEPT || (TABLES && ids)) ? (uint32_t)ids[c0 + si * (NW * kWave) + j * kWave + lane]
+                                        : bf(k[j]);
         const uint64_t mm = match_bucket<BITS>(b, ballot(valid));
         const uint32_t r = count_below(mm), cnt = popc64(mm);
         const uint32_t pos = lds_get(my_cnt + b);
@@ -368,11 +386,13 @@ postscan_kernel(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict
                           vals_out};
     const uint32_t ntiles = (uint32_t)(((uint64_t)len + T - 1) / T);
     const uint32_t wbase = wg * NW * kWave;
-    uint32_t k[NW], v[NW];
+    uint32_t k[NW], v[NW], idv[NW];
+    const bool use_ids = KEPT || (TABLES && ids != nullptr);
 
-    // Loads of tile ti into k, v (element (wg, j, lane) of the tile).  In a
-    // partial tile, lanes past the end read the tile's first element, which
-    // always exists, and are masked out later.
+    // Loads of tile ti into k, v (and the kept bucket ids into idv) --
+    // element (wg, j, lane) of the tile.  In a partial tile, lanes past the
+    // end read the tile's first element, which always exists, and are
+    // masked out later.
     auto load = [&](uint32_t ti, auto full_tag) {
       constexpr bool FULL = decltype(full_tag)::value;
       const uint32_t tb0 = c0 + ti * T;
@@ -388,6 +408,14 @@ postscan_kernel(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict
           const bool valid = wbase + (uint32_t)(j * kWave) + lane < tcount;
           k[j] = __builtin_nontemporal_load(valid ? pk + j * kWave : keys_in + tb0);
           if (KV) v[j] = __builtin_nontemporal_load(valid ? pv + j * kWave : vals_in + tb0);
+        }
+      }
+      if ((TABLES || KEPT) && use_ids) {
+        const uint8_t* pi = ids + tb0 + wbase + lane;
+#pragma unroll
+        for (int j = 0; j < NW; ++j) {
+          const bool valid = FULL || wbase + (uint32_t)(j * kWave) + lane < tcount;
+          idv[j] = __builtin_nontemporal_load(valid ? pi + j * kWave : ids + tb0);
         }
       }
     };
@@ -409,9 +437,11 @@ postscan_kernel(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict
         }
       };
       if constexpr (SMALL)
-        tile_small<BITS, KV, WPG, NW, FULL, REV>(bf, k, v, tb, tcount, wg, lane, run, next);
+        tile_small<BITS, KV, WPG, NW, FULL, REV>(bf, k, v, idv, use_ids, tb, tcount, wg, lane, run,
+                                                 next);
       else
-        tile_large<BITS, KV, WPG, NW, FULL, REV>(bf, k, v, tb, m, tcount, wg, lane, next);
+        tile_large<BITS, KV, WPG, NW, FULL, REV>(bf, k, v, idv, use_ids, tb, m, tcount, wg, lane,
+                                                 next);
     };
 
     if (ntiles > 0) load_tile(REV ? ntiles - 1 : 0);
@@ -423,7 +453,7 @@ postscan_kernel(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict
         tile(ti, std::false_type{});
     }
   }
-  if (Kind == kLearned && bp.mispredicts) {
+  if (Kind == kLearned && bp.mispredicts && !ids) {
     uint32_t miss = bf.misses();
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) miss += __shfl_xor(miss, d, kWave);

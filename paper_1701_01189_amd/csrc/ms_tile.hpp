@@ -129,16 +129,19 @@ struct TileBufs {
 // table-search kinds.  `my` is this wavefront's counter row, already zero.
 template <int BITS, int NW, bool FULL, class BF>
 __device__ __forceinline__ void rank_windows(const BF& bf, const uint32_t (&k)[NW],
+                                             const uint32_t (&idv)[NW], bool use_ids,
                                              uint32_t (&lr)[NW], uint32_t* my, uint32_t wbase,
                                              uint32_t lane, uint32_t tcount) {
   constexpr bool CHEAP = BF::kCheap;
   auto valid_at = [&](int j) { return FULL || wbase + (uint32_t)(j * kWave) + lane < tcount; };
   // Table-search ids are all computed first, so that their LDS probes
-  // overlap; cheap ids are computed one window ahead.
+  // overlap (or taken from the ids the pre-scan kept); cheap ids are
+  // computed one window ahead.
   uint32_t bk[CHEAP ? 1 : NW];
   if (!CHEAP) {
 #pragma unroll
-    for (int j = 0; j < NW; ++j) bk[CHEAP ? 0 : j] = valid_at(j) ? bf(k[j]) : 0u;
+    for (int j = 0; j < NW; ++j)
+      bk[CHEAP ? 0 : j] = valid_at(j) ? (use_ids ? idv[j] : bf(k[j])) : 0u;
   }
   auto bucket = [&](int j) -> uint32_t {
     if (CHEAP) return valid_at(j) ? bf(k[j]) : 0u;
@@ -204,6 +207,7 @@ __device__ __forceinline__ void write_back(const TileBufs<KV>& t, uint32_t tcoun
 // the end of what is left of the bucket's range (moved back over them).
 template <int BITS, bool KV, int WPG, int NW, bool FULL, bool REV, class BF, class After>
 __device__ __forceinline__ void tile_small(const BF& bf, uint32_t (&k)[NW], uint32_t (&v)[NW],
+                                           const uint32_t (&idv)[NW], bool use_ids,
                                            const TileBufs<KV>& t, uint32_t tcount, uint32_t wg,
                                            uint32_t lane, uint32_t& run, After after) {
   static_assert(BITS <= 6, "one bucket per lane");
@@ -214,7 +218,7 @@ __device__ __forceinline__ void tile_small(const BF& bf, uint32_t (&k)[NW], uint
   lds_put(my + lane, 0u);  // buckets >= m stay zero
   wave_order();
   uint32_t lr[NW];
-  rank_windows<BITS, NW, FULL>(bf, k, lr, my, wbase, lane, tcount);
+  rank_windows<BITS, NW, FULL>(bf, k, idv, use_ids, lr, my, wbase, lane, tcount);
   group_sync<WPG>();
 
   // step 2, lane = bucket: the group's count and this wavefront's prefix
@@ -259,6 +263,7 @@ __device__ __forceinline__ void tile_small(const BF& bf, uint32_t (&k)[NW], uint
 // it can finish the bucket's bookkeeping itself.
 template <int BITS, bool KV, int WPG, int NW, bool FULL, bool REV, class BF, class After>
 __device__ __forceinline__ void tile_large(const BF& bf, uint32_t (&k)[NW], uint32_t (&v)[NW],
+                                           const uint32_t (&idv)[NW], bool use_ids,
                                            const TileBufs<KV>& t, uint32_t m, uint32_t tcount,
                                            uint32_t wg, uint32_t lane, After after) {
   constexpr uint32_t S = kCntStride;
@@ -270,7 +275,7 @@ __device__ __forceinline__ void tile_large(const BF& bf, uint32_t (&k)[NW], uint
   for (uint32_t b = lane; b < m; b += kWave) lds_put(my + b, 0u);
   wave_order();
   uint32_t lr[NW];
-  rank_windows<BITS, NW, FULL>(bf, k, lr, my, wbase, lane, tcount);
+  rank_windows<BITS, NW, FULL>(bf, k, idv, use_ids, lr, my, wbase, lane, tcount);
   group_sync<WPG>();
 
   // step 2: buckets b0 .. b0 + bpt - 1 of this thread; their totals, an

@@ -248,11 +248,16 @@ hipError_t pre_by_kind(int kind, const ms::PreArgs& a, int bits) {
   }
 }
 
+// Post-scan kind: a table-search kind whose ids the pre-scan keeps runs the
+// post-scan that only reads them.
+constexpr int kPostKeptIds = ms::kKeptIds;
+
 hipError_t post_by_kind(int kind, const ms::PostArgs& a, int bits) {
   switch (kind) {
     case MS_BUCKET_SHIFT_MASK: return ms::post_shift_mask(a, bits);
     case MS_BUCKET_DIV: return ms::post_div(a, bits);
     case MS_BUCKET_SPLITTERS: return ms::post_splitters(a, bits);
+    case kPostKeptIds: return ms::post_kept_ids(a, bits);
     default: return ms::post_learned(a, bits);
   }
 }
@@ -387,11 +392,20 @@ ms_status run_multisplit(const uint32_t* ki, const uint32_t* vi, uint32_t* ko, u
     return MS_OK;
   }
   const int bits = (int)ceil_log2(m);
-  Plan p = make_plan(n, m, s, resident_groups(fn->kind, bits, kv, s));
+  // Bucket ids kept by the pre-scan (table-search kinds, on request): the
+  // last n bytes of the workspace.
+  uint8_t* ids = nullptr;
+  if (opt && opt->keep_bucket_ids && m <= (uint32_t)ms::kMaxBuckets &&
+      (fn->kind == MS_BUCKET_SPLITTERS || fn->kind == MS_BUCKET_LEARNED)) {
+    const size_t total = ms_workspace_size(kv ? MS_OP_PAIRS : MS_OP_KEYS, n, m, 0, opt);
+    ids = (uint8_t*)ws + (total - align_up(n, kWsAlign));
+  }
+  const int post_kind = ids ? kPostKeptIds : fn->kind;
+  Plan p = make_plan(n, m, s, resident_groups(post_kind, bits, kv, s));
   Workspace w = carve(ws, p);
   BucketParams bp = make_params(fn, m, opt ? opt->d_mispredicts : nullptr, div_mask);
   if (record(opt, 0, st) != hipSuccess) return MS_ERR_HIP;
-  ms::PreArgs pa{ki, p, bp, w.H, s.mode, s.hist, st};
+  ms::PreArgs pa{ki, p, bp, w.H, s.mode, s.hist, st, ids};
   if (pre_by_kind(fn->kind, pa, bits) != hipSuccess) return MS_ERR_HIP;
   if (record(opt, 1, st) != hipSuccess) return MS_ERR_HIP;
   // A small H (at most kRawH words, block-level reordering, up to 64
@@ -407,8 +421,9 @@ ms_status run_multisplit(const uint32_t* ki, const uint32_t* vi, uint32_t* ko, u
   // offsets are written by workgroup 0 of the post-scan; a NULL offsets
   // pointer is redirected to the spare words after the bucket totals.
   uint32_t* off = offsets ? offsets : w.totals + ms::kMaxBuckets;
-  ms::PostArgs qa{ki, vi, ko, vo, w.H, w.totals, off, p, bp, s.mode, s.wpb, s.nw, kv, st, nullptr};
-  if (post_by_kind(fn->kind, qa, bits) != hipSuccess) return MS_ERR_HIP;
+  ms::PostArgs qa{ki, vi, ko, vo, w.H, w.totals, off, p, bp, s.mode, s.wpb, s.nw, kv, st, nullptr,
+                  ids};
+  if (post_by_kind(post_kind, qa, bits) != hipSuccess) return MS_ERR_HIP;
   if (record(opt, 3, st) != hipSuccess) return MS_ERR_HIP;
   return MS_OK;
 }
@@ -601,10 +616,12 @@ size_t ms_workspace_size(int op, size_t n, uint32_t m, uint32_t num_inst, const 
       // The default shape depends on the bucket kind: size for both (a
       // shape that table-search kinds cannot run is sized for the others).
       Shape t;
+      const size_t ids = (op != MS_OP_HISTOGRAM && opt && opt->keep_bucket_ids)
+                             ? align_up(n, kWsAlign) : 0;  // kept bucket ids, last
       const size_t a = ms_ws_bytes(make_plan(n, m, s, 0));
-      if (resolve_shape(opt, n, m, MS_BUCKET_SPLITTERS, kv_op, &t) != MS_OK) return a;
+      if (resolve_shape(opt, n, m, MS_BUCKET_SPLITTERS, kv_op, &t) != MS_OK) return a + ids;
       const size_t b = ms_ws_bytes(make_plan(n, m, t, 0));
-      return a > b ? a : b;
+      return (a > b ? a : b) + ids;
     }
     case MS_OP_RADIX_SORT:
     case MS_OP_RADIX_SORT_PAIRS: {
@@ -678,12 +695,20 @@ ms_status ms_pairs_noalloc(const uint32_t* d_keys_in, const uint32_t* d_vals_in,
   Shape s;
   int sr = resolve_shape(opt, n, m, fn->kind, kv, &s);
   if (sr != MS_OK) return (ms_status)sr;
-  if (ms_workspace_size(kv ? MS_OP_PAIRS : MS_OP_KEYS, n, m, 0, opt) > kScratchBytes)
+  ms_options plain;
+  memset(&plain, 0, sizeof(plain));
+  if (opt) plain = *opt;
+  plain.keep_bucket_ids = 0;
+  if (ms_workspace_size(kv ? MS_OP_PAIRS : MS_OP_KEYS, n, m, 0, &plain) > kScratchBytes)
     return MS_ERR_WORKSPACE;
   void* ws = scratch_on_current_device();
   if (!ws) return MS_ERR_HIP;
+  ms_options o;  // (kept bucket ids would need n bytes: not in the static array)
+  memset(&o, 0, sizeof(o));
+  if (opt) o = *opt;
+  o.keep_bucket_ids = 0;
   return run_multisplit(d_keys_in, kv ? d_vals_in : nullptr, d_keys_out, d_vals_out, d_offsets,
-                        n, m, fn, ws, s, opt, (hipStream_t)stream);
+                        n, m, fn, ws, s, &o, (hipStream_t)stream);
 }
 
 ms_status ms_histogram(const uint32_t* d_keys, size_t n, uint32_t m, const ms_bucket_fn* fn,

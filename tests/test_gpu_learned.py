@@ -168,3 +168,69 @@ def test_range_2e27_lognormal_learned_full_size():
     k, o = ms.keys(dk, 256, ms.BucketFn.splitter(ds))
     np.testing.assert_array_equal(host(k), ek)
     np.testing.assert_array_equal(host(o), eo)
+
+
+@pytest.mark.parametrize("kv", [False, True])
+def test_kept_bucket_ids_match_oracle(kv):
+    """keep_bucket_ids: the pre-scan stores each key's bucket id and the
+    post-scan reads it; the output is the same unique stable multisplit, for
+    block (several tile shapes), wave-level and no reordering, on lognormal
+    keys over 256 range buckets and on uniform keys over 50 splitters (one
+    bucket per lane path); several tiles per chunk and a ragged tail."""
+    from paper_1701_01189_amd import binding as ms
+    n = (1 << 21) + 4097
+    keys, spl, fit = lognormal_setup(n)
+    model = oracle.learned_fit(fit, spl, 256)
+    vals = inputs.index_values(n) if kv else None
+    ek, ev, eo = oracle.multisplit(keys, 256, oracle.SPLITTERS, vals=vals, splitters=spl)
+    dk, ds, dm = dev(keys), dev(spl), devf(model)
+    dv = dev(vals) if kv else None
+    # (16 x 16 key-value tiles with their bucket ids do not fit in LDS)
+    shapes = [(1, 8, 8), (1, 16, 8), (2, 8, 8), (3, 8, 8)] + ([] if kv else [(1, 16, 16)])
+    for shape in shapes:
+        for name, fn in (("splitters", ms.BucketFn.splitter(ds)),
+                         ("learned", ms.BucketFn.learned(ds, dm))):
+            say("case kept ids %s kv=%s shape=%s" % (name, kv, shape))
+            opt = ms.Options(*shape, max_chunks=37, keep_bucket_ids=1)
+            if kv:
+                k, v, o = ms.pairs(dk, dv, 256, fn, options=opt)
+                np.testing.assert_array_equal(host(v), ev)
+            else:
+                k, o = ms.keys(dk, 256, fn, options=opt)
+            np.testing.assert_array_equal(host(k), ek)
+            np.testing.assert_array_equal(host(o), eo)
+    # m = 50 (a bucket per lane, 49 splitters), uniform keys
+    m = 50
+    ukeys = inputs.uniform_u32(151, n)
+    uspl = np.sort(inputs.uniform_u32(152, m - 1))
+    uvals = inputs.index_values(n) if kv else None
+    ek, ev, eo = oracle.multisplit(ukeys, m, oracle.SPLITTERS, vals=uvals, splitters=uspl)
+    dk, ds = dev(ukeys), dev(uspl)
+    dv = dev(uvals) if kv else None
+    for shape in [(1, 8, 8), (2, 8, 8), (3, 8, 8)]:
+        say("case kept ids m=50 kv=%s shape=%s" % (kv, shape))
+        opt = ms.Options(*shape, keep_bucket_ids=1)
+        if kv:
+            k, v, o = ms.pairs(dk, dv, m, ms.BucketFn.splitter(ds), options=opt)
+            np.testing.assert_array_equal(host(v), ev)
+        else:
+            k, o = ms.keys(dk, m, ms.BucketFn.splitter(ds), options=opt)
+        np.testing.assert_array_equal(host(k), ek)
+        np.testing.assert_array_equal(host(o), eo)
+
+
+def test_kept_bucket_ids_count_the_same_mispredictions():
+    """With kept ids the raw-model mispredictions are counted by the
+    pre-scan: the count equals the oracle's, as without kept ids."""
+    from paper_1701_01189_amd import binding as ms
+    n = (1 << 20) + 77
+    keys, spl, fit = lognormal_setup(n)
+    model = oracle.learned_fit(fit, spl, 256)
+    _, emiss = oracle.learned_bucket_ids(model, spl, 256, keys)
+    dk, ds, dm = dev(keys), dev(spl), devf(model)
+    for keep in (0, 1):
+        miss = torch.zeros(1, dtype=torch.int64, device="cuda")
+        ms.keys(dk, 256, ms.BucketFn.learned(ds, dm),
+                options=ms.Options(mispredicts=miss, keep_bucket_ids=keep))
+        torch.cuda.synchronize()
+        assert int(miss.item()) == int(emiss), (keep, int(miss.item()), int(emiss))

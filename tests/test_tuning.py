@@ -16,7 +16,7 @@ class Counting:
     def __init__(self, ms, **fields):
         self.ms, self.fields, self.calls = ms, fields, []
 
-    def __call__(self, op, keys_in, vals_in, m, fn=None, seg=None, reps=3):
+    def __call__(self, op, keys_in, vals_in, m, fn=None, seg=None, reps=3, base=None):
         self.calls.append((op, keys_in.numel(), vals_in is not None, m, reps))
         return self.ms.Options(**self.fields), 0.125
 
@@ -27,11 +27,11 @@ def keys(n):
 
 def test_cache_key_size_classes():
     from paper_1701_01189_amd import tuning
-    assert tuning._key(0, 1 << 20, 32, False, 0, 0) == "op0|m32|n2^20|kv0|kind0|inst0|gfx950"
+    assert tuning._key(0, 1 << 20, 32, False, 0, 0) == "op0|m32|n2^20|kv0|kind0|inst0|ids0|gfx950"
     assert tuning._key(0, (1 << 20) + 1, 32, False, 0, 0).split("|")[2] == "n2^21"
     assert tuning._key(0, (1 << 19) + 1, 32, False, 0, 0).split("|")[2] == "n2^20"
-    assert tuning._key(1, 1, 256, True, 2, 0) == "op1|m256|n2^0|kv1|kind2|inst0|gfx950"
-    assert tuning._key(2, 1000, 64, True, 0, 4096).endswith("|inst13|gfx950")
+    assert tuning._key(1, 1, 256, True, 2, 0) == "op1|m256|n2^0|kv1|kind2|inst0|ids0|gfx950"
+    assert tuning._key(2, 1000, 64, True, 0, 4096).endswith("|inst13|ids0|gfx950")
     # every field separates entries
     base = tuning._key(1, 5000, 32, True, 1, 0)
     for other in (tuning._key(0, 5000, 32, True, 1, 0), tuning._key(1, 5000, 16, True, 1, 0),
@@ -51,7 +51,7 @@ def test_miss_measures_and_stores_then_hit_reads(tmp_path, monkeypatch):
     assert stub.calls == [(ms.OP_KEYS, 3000, False, 32, 2)]
     assert (opt.reorder, opt.waves_per_block, opt.items_per_lane, opt.prescan) == (2, 4, 16, 1)
     table = json.load(open(cache))
-    assert table == {"op0|m32|n2^12|kv0|kind1|inst0|gfx950": e}
+    assert table == {"op0|m32|n2^12|kv0|kind1|inst0|ids0|gfx950": e}
     assert e["ms"] == 0.125
     opt2, e2 = tuning.tuned_options(ms.OP_KEYS, keys(2100), None, 32, fn=fn, cache=cache)
     assert len(stub.calls) == 1 and e2 == e  # same size class: read from the cache
