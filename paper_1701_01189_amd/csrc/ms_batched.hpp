@@ -42,6 +42,8 @@ struct BatchedArgs {
   uint32_t claim;        // work items per queue claim
   uint32_t spin_limit;   // polls before a wait gives up
   uint32_t never_ready;  // test hook: never raise ready flags (forces timeouts)
+  uint32_t osh;          // 2: total <= 2^30, output positions as byte offsets
+  uint32_t ntl;          // 1: whole output lines stored nontemporally
   BucketParams bp;
 };
 
@@ -353,7 +355,7 @@ __global__ void __launch_bounds__(WPB* kWave) batched_kernel(BatchedArgs a) {
       const uint32_t tcount = r.y;
       const uint32_t* Hi = a.H + (size_t)m * (tg - t);
       const TileBufs<KV> tb{s_reorder, s_vals, s_cnt, s_run, s_delta, s_tmp, a.keys_out,
-                            a.vals_out};
+                            a.vals_out, a.osh, a.ntl};
       const uint32_t idv[NW] = {};  // (bucket ids are computed here)
       // the next item's loads go out once this tile sits in LDS
       auto next = [&] { if (it + 1 < last) load_item(it + 1, std::true_type{}); };

@@ -25,6 +25,8 @@ struct Plan {
   uint32_t tile;      // elements per tile
   uint32_t h_raw;     // 1: H is not scanned; every post-scan workgroup reads it
                       // whole (block-level reordering, at most 64 buckets)
+  uint32_t nt_lines;  // 1: whole output lines are stored nontemporally (at most
+                      // 64 buckets)
 };
 
 // ---------------------------------------------------------------------------
@@ -72,7 +74,8 @@ prescan_kernel(const uint32_t* __restrict__ keys, Plan plan, BucketParams bp,
   const uint32_t lane = lane_id();
   const LaneSel ls(lane);
   const uint32_t w = wave_id();
-  const uint32_t g = w / WPG, wg = w % WPG;
+  // (one group per workgroup: its LDS offsets are then constants)
+  const uint32_t g = GPB == 1 ? 0u : w / WPG, wg = GPB == 1 ? w : w % WPG;
   const uint32_t c = blockIdx.x * GPB + g;
   // The chunk's count of bucket b goes to its column of H.
   auto emit = [&](uint32_t b, uint32_t v) { H[b * plan.L0 + c] = v; };
@@ -246,7 +249,8 @@ postscan_kernel(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict
 
   const uint32_t lane = lane_id();
   const uint32_t w = wave_id();
-  const uint32_t g = w / WPG, wg = w % WPG;
+  // (one group per workgroup: its LDS offsets are then constants)
+  const uint32_t g = GPB == 1 ? 0u : w / WPG, wg = GPB == 1 ? w : w % WPG;
   const uint32_t m = plan.m;
   const uint32_t c = blockIdx.x * GPB + g;
 
@@ -383,7 +387,9 @@ postscan_kernel(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict
                           s_delta + (SMALL ? 0 : g * kMaxBuckets),
                           s_tmp + g * WPG,
                           keys_out,
-                          vals_out};
+                          vals_out,
+                          plan.n <= (1u << 30) ? 2u : 0u,
+                          plan.nt_lines};
     const uint32_t ntiles = (uint32_t)(((uint64_t)len + T - 1) / T);
     const uint32_t wbase = wg * NW * kWave;
     uint32_t k[NW], v[NW], idv[NW];
@@ -393,21 +399,35 @@ postscan_kernel(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict
     // element (wg, j, lane) of the tile.  In a partial tile, lanes past the
     // end read the tile's first element, which always exists, and are
     // masked out later.
+    // A lane's address is a uniform base (scalar registers) plus its 32-bit
+    // byte offset, and in a whole tile the window's distance is the
+    // instruction's immediate offset.  The lane offset passes through an
+    // empty volatile asm so that it is not hoisted out of the tile loop as
+    // eight 64-bit addresses.
     auto load = [&](uint32_t ti, auto full_tag) {
       constexpr bool FULL = decltype(full_tag)::value;
       const uint32_t tb0 = c0 + ti * T;
       const uint32_t tcount = FULL ? (uint32_t)T : min((uint32_t)T, len - ti * T);
-      const uint32_t* pk = keys_in + tb0 + wbase + lane;
-      const uint32_t* pv = vals_in + tb0 + wbase + lane;
+      if (FULL) {
+        const char* kb = reinterpret_cast<const char*>(keys_in + tb0 + wbase);
+        const char* vb = reinterpret_cast<const char*>(vals_in + tb0 + wbase);
+        uint32_t lo = lane * 4u;
+        asm volatile("" : "+v"(lo));
 #pragma unroll
-      for (int j = 0; j < NW; ++j) {
-        if (FULL) {
-          k[j] = __builtin_nontemporal_load(pk + j * kWave);
-          if (KV) v[j] = __builtin_nontemporal_load(pv + j * kWave);
-        } else {
-          const bool valid = wbase + (uint32_t)(j * kWave) + lane < tcount;
-          k[j] = __builtin_nontemporal_load(valid ? pk + j * kWave : keys_in + tb0);
-          if (KV) v[j] = __builtin_nontemporal_load(valid ? pv + j * kWave : vals_in + tb0);
+        for (int j = 0; j < NW; ++j) {
+          const size_t off = (size_t)lo + (size_t)(j * kWave * 4);
+          k[j] = __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(kb + off));
+          if (KV) v[j] = __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(vb + off));
+        }
+      } else {
+        const char* kb = reinterpret_cast<const char*>(keys_in + tb0);
+        const char* vb = reinterpret_cast<const char*>(vals_in + tb0);
+#pragma unroll
+        for (int j = 0; j < NW; ++j) {
+          const uint32_t e = wbase + (uint32_t)(j * kWave) + lane;  // element of the tile
+          const size_t off = e < tcount ? (size_t)e * 4u : 0u;
+          k[j] = __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(kb + off));
+          if (KV) v[j] = __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(vb + off));
         }
       }
       if ((TABLES || KEPT) && use_ids) {
@@ -431,7 +451,8 @@ postscan_kernel(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict
       const uint32_t tcount = FULL ? (uint32_t)T : min((uint32_t)T, len - ti * T);
       auto next = [&] {
         if (REV) {
-          if (ti > 0) load_tile(ti - 1);
+          // only a chunk's last tile can be partial
+          if (ti > 0) load(ti - 1, std::true_type{});
         } else if (ti + 1 < ntiles) {
           load_tile(ti + 1);
         }

@@ -39,6 +39,8 @@
 // step 4 looks up the bucket's output offset.
 #pragma once
 
+#include <type_traits>
+
 #include "ms_device.hpp"
 
 namespace ms {
@@ -121,6 +123,13 @@ struct TileBufs {
   uint32_t* tmp;      // above 64 buckets: WPG words
   uint32_t* keys_out;
   uint32_t* vals_out;
+  // Output positions are carried as byte offsets (shift 2) when every output
+  // index is below 2^30: a 32-bit offset from the uniform output base then
+  // addresses the store directly.  Shift 0: element indices.
+  uint32_t osh;
+  // 1: elements of whole output lines are stored nontemporally (with byte
+  // offsets only; see tile_small)
+  uint32_t ntl;
 };
 
 // Step 1 for the group's tile: fills lr[j] with the element's rank among
@@ -190,13 +199,39 @@ template <bool KV, int GT, int NW, bool FULL>
 __device__ __forceinline__ void write_back(const TileBufs<KV>& t, uint32_t tcount,
                                            uint32_t tid_g) {
   const uint2* s_ko = static_cast<const uint2*>(t.buf);
+  if (t.osh) {
+    char* kb = reinterpret_cast<char*>(t.keys_out);
+    char* vb = reinterpret_cast<char*>(t.vals_out);
 #pragma unroll
-  for (int j = 0; j < NW; ++j) {
-    const uint32_t q = (uint32_t)j * GT + tid_g;
-    if (FULL || q < tcount) {
-      const uint2 ko = s_ko[q];
-      t.keys_out[ko.y] = ko.x;
-      if (KV) t.vals_out[ko.y] = t.s_v[q];
+    for (int j = 0; j < NW; ++j) {
+      const uint32_t q = (uint32_t)j * GT + tid_g;
+      if (FULL || q < tcount) {
+        const uint2 ko = s_ko[q];
+        const size_t off = ko.y & ~3u;  // bit 0: a whole line, stored nontemporally
+        uint32_t* pk = reinterpret_cast<uint32_t*>(kb + off);
+        uint32_t* pv = reinterpret_cast<uint32_t*>(vb + off);
+        if (ko.y & 1u) {
+          // (the empty asm keeps the compiler from merging the two branches'
+          // stores into one ordinary store)
+          asm volatile("");
+          __builtin_nontemporal_store(ko.x, pk);
+          if (KV) __builtin_nontemporal_store(t.s_v[q], pv);
+          asm volatile("");
+        } else {
+          *pk = ko.x;
+          if (KV) *pv = t.s_v[q];
+        }
+      }
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < NW; ++j) {
+      const uint32_t q = (uint32_t)j * GT + tid_g;
+      if (FULL || q < tcount) {
+        const uint2 ko = s_ko[q];
+        t.keys_out[ko.y] = ko.x;
+        if (KV) t.vals_out[ko.y] = t.s_v[q];
+      }
     }
   }
 }
@@ -230,23 +265,46 @@ __device__ __forceinline__ void tile_small(const BF& bf, uint32_t (&k)[NW], uint
     pre += (w2 < (int)wg) ? x : 0u;
   }
   const uint32_t start = wave_inclusive_scan(tot, lane) - tot;  // tile slot of the bucket
-  const uint32_t base = start + pre;  // this wavefront's first slot of the bucket
+  // this wavefront's first slot of the bucket, as a byte offset in the buffer
+  const uint32_t base8 = (start + pre) * (uint32_t)sizeof(uint2);
   if (REV) run -= tot;
-  const uint32_t first = run + pre;   // ... and that element's output position
+  // ... and that element's output position (scaled as t.osh says)
+  const uint32_t first = (run + pre) << t.osh;
+  // With byte offsets: the whole 128-byte output lines inside the tile's run
+  // of the bucket ([run, run + tot) here), as [lo, lo + span) with lo taken
+  // relative to this wavefront's first position, in words: low half
+  // (first - lo) / 4 + 32 (at least 1), high half span / 4.  Elements there
+  // are stored nontemporally: their lines are complete, and the stores do not
+  // stay in the caches as dirty lines that the next pass over the input has
+  // to write back.  Elements of partial lines keep ordinary stores, which
+  // merge with the neighbouring tile's run in L2.
+  uint32_t lines = 0;
+  if (t.osh && t.ntl) {
+    const uint32_t lo = ((run << 2) + 127u) & ~127u, hi = ((run + tot) << 2) & ~127u;
+    const uint32_t span = hi > lo ? (hi - lo) >> 2 : 0u;
+    lines = ((uint32_t)((int32_t)(first - lo) >> 2) + 32u) | (span << 16);
+  }
   if (!REV) run += tot;
 
   // step 3: slot and output position of every element
+  char* buf = static_cast<char*>(t.buf);
+  char* vbuf = reinterpret_cast<char*>(t.s_v);
 #pragma unroll
   for (int j = 0; j < NW; ++j) {
     const bool valid = FULL || wbase + (uint32_t)(j * kWave) + lane < tcount;
     // (an invalid lane holds the tile's first key: its id is in range)
     const uint32_t bj = bucket_of(bf, k[j], lr[j]);
     const uint32_t r = rank_of<BF>(lr[j]);
-    const uint32_t slot = from_lane(base, bj) + r;
-    const uint32_t o = from_lane(first, bj) + r;
+    const uint32_t a = from_lane(base8, bj) + (r << 3);
+    uint32_t o = from_lane(first, bj) + (r << t.osh);
+    {
+      // bit 0 of a byte offset: the element's line is whole (see `lines`)
+      const uint32_t x = from_lane(lines, bj);
+      o |= ((x & 0xFFFFu) + r - 32u < (x >> 16)) ? 1u : 0u;
+    }
     if (valid) {
-      static_cast<uint2*>(t.buf)[slot] = make_uint2(k[j], o);
-      if (KV) t.s_v[slot] = v[j];
+      *reinterpret_cast<uint2*>(buf + a) = make_uint2(k[j], o);
+      if (KV) *reinterpret_cast<uint32_t*>(vbuf + (a >> 1)) = v[j];
     }
   }
   after();  // k, v are free: the next tile's loads go out
@@ -316,9 +374,9 @@ __device__ __forceinline__ void tile_large(const BF& bf, uint32_t (&k)[NW], uint
         }
         if (REV) {
           t.run[b] -= tot[i];
-          t.delta[b] = t.run[b] - st;
+          t.delta[b] = (t.run[b] - st) << t.osh;
         } else {
-          t.delta[b] = t.run[b] - st;
+          t.delta[b] = (t.run[b] - st) << t.osh;
           t.run[b] += tot[i];
         }
       }
@@ -346,18 +404,34 @@ __device__ __forceinline__ void tile_large(const BF& bf, uint32_t (&k)[NW], uint
   after();
   group_sync<WPG>();
 
-  // step 4: slot q of bucket b goes to delta[b] + q
+  // step 4: slot q of bucket b goes to delta[b] + q (both scaled by t.osh;
+  // modulo 2^32 the difference is exact)
+  auto step4 = [&](auto byte_tag) {
+    constexpr bool BYTES = decltype(byte_tag)::value;
 #pragma unroll
-  for (int j = 0; j < NW; ++j) {
-    const uint32_t q = (uint32_t)j * GT + tid_g;
-    if (FULL || q < tcount) {
-      uint32_t key = s_k[q];
-      const uint32_t bq = CHEAP ? recompute(bf, key) : (uint32_t)s_b[q];
-      const uint32_t o = t.delta[bq] + q;
-      t.keys_out[o] = key;
-      if (KV) t.vals_out[o] = t.s_v[q];
+    for (int j = 0; j < NW; ++j) {
+      const uint32_t q = (uint32_t)j * GT + tid_g;
+      if (FULL || q < tcount) {
+        uint32_t key = s_k[q];
+        const uint32_t bq = CHEAP ? recompute(bf, key) : (uint32_t)s_b[q];
+        if (BYTES) {
+          const uint32_t o = t.delta[bq] + (q << 2);
+          *reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(t.keys_out) + (size_t)o) = key;
+          if (KV)
+            *reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(t.vals_out) + (size_t)o) =
+                t.s_v[q];
+        } else {
+          const uint32_t o = t.delta[bq] + q;
+          t.keys_out[o] = key;
+          if (KV) t.vals_out[o] = t.s_v[q];
+        }
+      }
     }
-  }
+  };
+  if (t.osh)
+    step4(std::true_type{});
+  else
+    step4(std::false_type{});
   // No closing barrier (as in tile_small): counters, run and delta are next
   // written after the next tile's first barrier, tmp after its first too.
 }

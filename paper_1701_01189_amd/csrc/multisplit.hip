@@ -161,6 +161,7 @@ Plan make_plan(size_t n, uint32_t m, const Shape& s, uint32_t groups) {
   p.L0 = (uint32_t)L0;
   p.chunk = (uint32_t)(tpc * p.tile);
   p.h_raw = 0;
+  p.nt_lines = 0;
   return p;
 }
 
@@ -381,6 +382,19 @@ uint32_t resident_groups(int kind, int bits, bool kv, const Shape& s) {
 
 constexpr size_t kRawH = 4096;
 
+// Whole output lines stored nontemporally (block- and wavefront-level tiles up
+// to 64 buckets).  Measured on MI355X: such lines then do not sit dirty in
+// the caches for the next pass over the input to write back (2^28 keys,
+// m = 32: pre-scan 265 -> 241 us, whole call +3 %; 2^25 pairs +9 %), but
+// with 16-wavefront tiles on large inputs the post-scan loses more than the
+// pre-scan gains (2^28 pairs, 16 x 8: -2 to -8 %), and inputs that stay in
+// the caches gain nothing.
+constexpr size_t kNtMin = (size_t)1 << 22;
+bool nt_lines(size_t n, const Shape& s) {
+  if (n < kNtMin) return false;
+  return !(s.wpb > 8 && n > ((size_t)1 << 26));
+}
+
 // The three stages for one multisplit on already validated arguments.
 ms_status run_multisplit(const uint32_t* ki, const uint32_t* vi, uint32_t* ko, uint32_t* vo,
                          uint32_t* offsets, size_t n, uint32_t m, const ms_bucket_fn* fn,
@@ -412,6 +426,7 @@ ms_status run_multisplit(const uint32_t* ki, const uint32_t* vi, uint32_t* ko, u
   // buckets) is summed by every post-scan workgroup itself: one launch less
   // for inputs that take microseconds.
   p.h_raw = (s.mode == ms::kBlock && m <= 64 && (size_t)m * p.L0 <= kRawH) ? 1u : 0u;
+  p.nt_lines = nt_lines(n, s) ? 1u : 0u;
   if (!p.h_raw) {
     hipLaunchKernelGGL(ms::scan_rows_kernel, dim3(m), dim3(ms::kScanThreads), 0, st, w.H, p.L0,
                        w.totals);
@@ -845,6 +860,8 @@ ms_status ms_batched(const uint32_t* d_keys_in, const uint32_t* d_vals_in, uint3
   a.claim = bs.claim;
   a.spin_limit = bs.spin_limit;
   a.never_ready = bs.never_ready;
+  a.osh = total <= ((size_t)1 << 30) ? 2u : 0u;
+  a.ntl = total >= kNtMin ? 1u : 0u;
   a.bp = make_params(fn, m, opt ? opt->d_mispredicts : nullptr);
   const int bits = (int)ceil_log2(m);
   hipStream_t st = (hipStream_t)stream;
