@@ -316,11 +316,16 @@ def time_calls(step, K, warmup, stages=True, graph=False):
         hev = HipEvents(4 * K)
         evs = [[_Handle(hev.ev[4 * i + j]) for j in range(4)] for i in range(K)]
         torch.cuda.synchronize()
+        t0.record(stream)
         for i in range(K):
             step(evs[i])
+        t1.record(stream)
         torch.cuda.synchronize()
         out["stage"] = [sum(hev.ms(4 * i + s, 4 * i + s + 1) for i in range(K)) / K
                         for s in range(3)]
+        # per call in the second pass (the one that records the stage events):
+        # the first timed calls after the warm-up run slower than later ones
+        out["stage_pass_ms"] = t0.elapsed_time(t1) / K
         hev.close()
     if graph:
         side = torch.cuda.Stream()
@@ -408,6 +413,8 @@ def multisplit_row(args, name, dk, dv, m, fn, shape=(0, 0, 0), graph=False, cpu=
                              post_ms, ceiling),
         "whole_call": whole_call(n, kv, call_ms, passes),
     }
+    if "stage_pass_ms" in t:
+        row["second_pass_ms_per_call"] = round(t["stage_pass_ms"], 5)
     if radix_bits:
         row["passes"] = passes
         row["stage_ms_note"] = "stages of the last pass"
