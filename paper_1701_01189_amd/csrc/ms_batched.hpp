@@ -147,7 +147,7 @@ __global__ void __launch_bounds__(WPB* kWave) batched_kernel(BatchedArgs a) {
   // counter rows of the pre-scan's histogram and of the post-scan tiles
   __shared__ uint32_t s_cnt[WPB * kCntStride];
   __shared__ uint32_t s_run[kMaxBuckets];
-  __shared__ uint32_t s_delta[kMaxBuckets];
+  __shared__ __align__(8) uint32_t s_delta[2 * kMaxBuckets];
   constexpr int SLOT = reorder_bytes_per_slot<(BITS <= 6), !TABLES>();
   __shared__ uint64_t s_reorder[(T * SLOT + 7) / 8];
   __shared__ uint32_t s_vals[KV ? T : 1];

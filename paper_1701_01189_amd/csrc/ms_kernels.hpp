@@ -25,8 +25,7 @@ struct Plan {
   uint32_t tile;      // elements per tile
   uint32_t h_raw;     // 1: H is not scanned; every post-scan workgroup reads it
                       // whole (block-level reordering, at most 64 buckets)
-  uint32_t nt_lines;  // 1: whole output lines are stored nontemporally (at most
-                      // 64 buckets)
+  uint32_t nt_lines;  // 1: whole output lines are stored nontemporally
 };
 
 // ---------------------------------------------------------------------------
@@ -213,7 +212,7 @@ constexpr size_t postscan_lds_bytes() {
   constexpr size_t SLOT = reorder_bytes_per_slot<SMALL, Bucket<Kind, BITS>::kCheap>();
   return (TABLES ? (sizeof(BucketLds) + 3) / 4 * 4 : 4) +
          (size_t)WPB * (SMALL ? kWave : kCntStride) * 4 + (SMALL ? 4 : GPB * kMaxBuckets * 4) +
-         ((REORDER && !SMALL) ? GPB * kMaxBuckets * 4 : 4) +
+         ((REORDER && !SMALL) ? GPB * kMaxBuckets * (KV ? 8 : 4) : 8) +
          (REORDER ? (GPB * T * SLOT + 7) / 8 * 8 : 8) + ((REORDER && KV) ? GPB * T * 4 : 4) +
          (size_t)WPB * 4;
 }
@@ -240,7 +239,7 @@ postscan_kernel(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict
   __shared__ uint32_t s_tables[TABLES ? (sizeof(BucketLds) + 3) / 4 : 1];
   __shared__ uint32_t s_cnt[WPB * S];
   __shared__ uint32_t s_run[SMALL ? 1 : GPB * kMaxBuckets];
-  __shared__ uint32_t s_delta[(REORDER && !SMALL) ? GPB * kMaxBuckets : 1];
+  __shared__ __align__(8) uint32_t s_delta[(REORDER && !SMALL) ? GPB * (KV ? 2 : 1) * kMaxBuckets : 2];
   constexpr int SLOT = reorder_bytes_per_slot<SMALL, Bucket<Kind, BITS>::kCheap>();
   __shared__ uint64_t s_reorder[REORDER ? (GPB * T * SLOT + 7) / 8 : 1];
   __shared__ uint32_t s_vals[(REORDER && KV) ? GPB * T : 1];
@@ -384,7 +383,7 @@ postscan_kernel(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict
                           s_vals + (KV ? g * T : 0),
                           s_cnt + (g * WPG) * S,
                           grun,
-                          s_delta + (SMALL ? 0 : g * kMaxBuckets),
+                          s_delta + (SMALL ? 0 : g * (KV ? 2 : 1) * kMaxBuckets),
                           s_tmp + g * WPG,
                           keys_out,
                           vals_out,

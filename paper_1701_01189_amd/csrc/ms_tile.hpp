@@ -119,7 +119,8 @@ struct TileBufs {
   uint32_t* s_v;      // reorder buffer [T]: values
   uint32_t* cnt;      // the group's counters, wavefront wg's row at wg * stride
   uint32_t* run;      // above 64 buckets: [m] running output position
-  uint32_t* delta;    // above 64 buckets: [m] output position minus slot
+  uint32_t* delta;    // above 64 buckets: [m] output position minus slot (key-value
+                      // tiles: pairs of it and the whole-line slots, first | count << 16)
   uint32_t* tmp;      // above 64 buckets: WPG words
   uint32_t* keys_out;
   uint32_t* vals_out;
@@ -372,12 +373,27 @@ __device__ __forceinline__ void tile_large(const BF& bf, uint32_t (&k)[NW], uint
           t.cnt[w2 * S + b] = acc;
           acc += x;
         }
+        uint32_t rb;  // the bucket's first output position in this tile
         if (REV) {
-          t.run[b] -= tot[i];
-          t.delta[b] = (t.run[b] - st) << t.osh;
+          rb = t.run[b] - tot[i];
+          t.run[b] = rb;
         } else {
-          t.delta[b] = (t.run[b] - st) << t.osh;
-          t.run[b] += tot[i];
+          rb = t.run[b];
+          t.run[b] = rb + tot[i];
+        }
+        if (KV) {
+          // The slots whose output lines (32 elements, 128 bytes) lie wholly
+          // inside the tile's run [rb, rb + tot): stored nontemporally
+          // (key-value tiles only: key-only ones measured slower with it).
+          uint32_t wl = 0;
+          if (t.osh && t.ntl) {
+            const uint32_t l0 = (rb + 31u) & ~31u, l1 = (rb + tot[i]) & ~31u;
+            if (l1 > l0) wl = (st + (l0 - rb)) | ((l1 - l0) << 16);
+          }
+          t.delta[2 * b] = (rb - st) << t.osh;
+          t.delta[2 * b + 1] = wl;
+        } else {
+          t.delta[b] = (rb - st) << t.osh;
         }
       }
       pre += tot[i];
@@ -414,14 +430,23 @@ __device__ __forceinline__ void tile_large(const BF& bf, uint32_t (&k)[NW], uint
       if (FULL || q < tcount) {
         uint32_t key = s_k[q];
         const uint32_t bq = CHEAP ? recompute(bf, key) : (uint32_t)s_b[q];
+        const uint2 dw = KV ? reinterpret_cast<const uint2*>(t.delta)[bq]
+                            : make_uint2(t.delta[bq], 0u);
         if (BYTES) {
-          const uint32_t o = t.delta[bq] + (q << 2);
-          *reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(t.keys_out) + (size_t)o) = key;
-          if (KV)
-            *reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(t.vals_out) + (size_t)o) =
-                t.s_v[q];
+          const uint32_t o = dw.x + (q << 2);
+          uint32_t* pk = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(t.keys_out) + (size_t)o);
+          uint32_t* pv = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(t.vals_out) + (size_t)o);
+          if (KV && q - (dw.y & 0xFFFFu) < (dw.y >> 16)) {
+            asm volatile("");  // (as in write_back: two stores, not one)
+            __builtin_nontemporal_store(key, pk);
+            if (KV) __builtin_nontemporal_store(t.s_v[q], pv);
+            asm volatile("");
+          } else {
+            *pk = key;
+            if (KV) *pv = t.s_v[q];
+          }
         } else {
-          const uint32_t o = t.delta[bq] + q;
+          const uint32_t o = dw.x + q;
           t.keys_out[o] = key;
           if (KV) t.vals_out[o] = t.s_v[q];
         }

@@ -59,7 +59,7 @@ size_t post_lds_bytes(const Shape& s, uint32_t m, int kind, bool kv) {
   size_t b = tables ? sizeof(ms::BucketLds) : 4;
   b += (size_t)s.wpb * (small ? ms::kWave : ms::kCntStride) * 4;
   b += small ? 4 : gpb * ms::kMaxBuckets * 4;
-  b += (reorder && !small) ? gpb * ms::kMaxBuckets * 4 : 4;
+  b += (reorder && !small) ? gpb * ms::kMaxBuckets * (kv ? 8 : 4) : 8;
   b += reorder ? (gpb * T * slot + 7) / 8 * 8 : 8;
   b += (reorder && kv) ? gpb * T * 4 : 4;
   b += (size_t)s.wpb * 4;
@@ -382,16 +382,20 @@ uint32_t resident_groups(int kind, int bits, bool kv, const Shape& s) {
 
 constexpr size_t kRawH = 4096;
 
-// Whole output lines stored nontemporally (block- and wavefront-level tiles up
-// to 64 buckets).  Measured on MI355X: such lines then do not sit dirty in
+// Whole output lines stored nontemporally.  Measured on MI355X: such lines then do not sit dirty in
 // the caches for the next pass over the input to write back (2^28 keys,
 // m = 32: pre-scan 265 -> 241 us, whole call +3 %; 2^25 pairs +9 %), but
 // with 16-wavefront tiles on large inputs the post-scan loses more than the
 // pre-scan gains (2^28 pairs, 16 x 8: -2 to -8 %), and inputs that stay in
 // the caches gain nothing.
 constexpr size_t kNtMin = (size_t)1 << 22;
-bool nt_lines(size_t n, const Shape& s) {
+bool nt_lines(size_t n, uint32_t m, bool kv, const Shape& s) {
   if (n < kNtMin) return false;
+  // Above 64 buckets the runs are short and only key-value tiles gain
+  // (2^28 pairs, m = 256: 164.6 -> 170.5 Gpairs/s, radix sort 41.1 -> 42.5;
+  // keys m = 256: 281.0 -> 276.6 Gkeys/s); key-only tiles there do not
+  // carry the whole-line bounds at all.
+  if (m > 64) return kv;
   return !(s.wpb > 8 && n > ((size_t)1 << 26));
 }
 
@@ -426,7 +430,7 @@ ms_status run_multisplit(const uint32_t* ki, const uint32_t* vi, uint32_t* ko, u
   // buckets) is summed by every post-scan workgroup itself: one launch less
   // for inputs that take microseconds.
   p.h_raw = (s.mode == ms::kBlock && m <= 64 && (size_t)m * p.L0 <= kRawH) ? 1u : 0u;
-  p.nt_lines = nt_lines(n, s) ? 1u : 0u;
+  p.nt_lines = nt_lines(n, m, kv, s) ? 1u : 0u;
   if (!p.h_raw) {
     hipLaunchKernelGGL(ms::scan_rows_kernel, dim3(m), dim3(ms::kScanThreads), 0, st, w.H, p.L0,
                        w.totals);
