@@ -774,6 +774,7 @@ def headline(args, dev):
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "device_warmup_ms": DEVICE_WARMUP_MS,
         "ms_per_step": head["ms_per_call"],
         "higher_is_better": True,
         "scaling": "weak",
@@ -814,7 +815,8 @@ def headline(args, dev):
 def single_line(args, row, extra_config=None):
     line = {
         "metric": METRIC, "value": row["value"], "unit": row["unit"], "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": row["ms_per_call"],
+        "steps": args.steps, "warmup": args.warmup, "device_warmup_ms": DEVICE_WARMUP_MS,
+        "ms_per_step": row["ms_per_call"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": row["workload"], **(extra_config or {})},
