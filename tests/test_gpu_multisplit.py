@@ -256,3 +256,36 @@ def test_identity_buckets_sort_small_keys(bits):
         np.testing.assert_array_equal(host(k), ek)
         np.testing.assert_array_equal(host(v), ev)
         np.testing.assert_array_equal(host(o), eo)
+
+
+@pytest.mark.parametrize("m,kv", [(8, False), (32, False), (32, True), (128, True)])
+def test_whole_line_stores(m, kv):
+    """From 2^22 elements on, the elements of whole 128-byte output lines are
+    stored nontemporally (up to 64 buckets; key-value tiles above).  Ragged n,
+    several tile shapes, and outputs that start 4 bytes past a line boundary,
+    where the whole-line test no longer matches the real lines: still exact."""
+    from paper_1701_01189_amd import binding as ms
+    n = (1 << 22) + 777
+    keys = inputs.uniform_u32(120 + m, n)
+    vals = inputs.index_values(n)
+    shift = 32 - (m - 1).bit_length()
+    ek, ev, eo = oracle.multisplit(keys, m, oracle.SHIFT_MASK, vals=vals if kv else None,
+                                   shift=shift, mask=m - 1)
+    dk, dv = dev(keys), dev(vals)
+    fn = ms.BucketFn.shift_mask(shift, m - 1)
+    for off in (0, 1):
+        for shape in [(1, 8, 8), (1, 4, 16), (1, 16, 8), (0, 0, 0)]:
+            say("case whole lines m=%d kv=%d offset=%d shape=%s" % (m, kv, off, shape))
+            kbuf = torch.zeros(n + 1, dtype=torch.int32, device="cuda")
+            vbuf = torch.zeros(n + 1, dtype=torch.int32, device="cuda")
+            ko, vo = kbuf[off:off + n], vbuf[off:off + n]
+            if kv:
+                ms.pairs(dk, dv, m, fn, keys_out=ko, vals_out=vo, options=ms.Options(*shape))
+                np.testing.assert_array_equal(host(vo), ev)
+                k, o = ko, None
+            else:
+                k, o = ms.keys(dk, m, fn, keys_out=ko, options=ms.Options(*shape))
+                np.testing.assert_array_equal(host(o), eo)
+            np.testing.assert_array_equal(host(k), ek)
+            # nothing outside the output
+            assert int(kbuf[n if off == 0 else 0].item()) == 0
