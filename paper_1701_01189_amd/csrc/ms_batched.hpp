@@ -245,8 +245,18 @@ __global__ void __launch_bounds__(WPB* kWave) batched_kernel(BatchedArgs a) {
       }
       __syncthreads();
     };
-    if (first < pre_end) load_item(first, std::false_type{});
-    for (uint32_t it = first; it < pre_end; ++it) {
+    // ---- pre-scan items: keys only, two items ahead ----
+    uint32_t k2[NW];
+    auto load_keys = [&](uint32_t it, uint32_t (&dst)[NW]) {
+      const uint4 r = s_info[it - first];
+      const uint32_t* pk = a.keys_in + r.x + wbase + lane;
+#pragma unroll
+      for (int j = 0; j < NW; ++j) {
+        const bool valid = wbase + (uint32_t)(j * kWave) + lane < r.y;
+        dst[j] = __builtin_nontemporal_load(valid ? pk + j * kWave : a.keys_in + r.x);
+      }
+    };
+    auto pre_item = [&](uint32_t it, uint32_t (&kc)[NW]) {
       const uint4 r = s_info[it - first];
       const uint32_t i = r.z;
       if (i != pub_inst) {
@@ -261,19 +271,17 @@ __global__ void __launch_bounds__(WPB* kWave) batched_kernel(BatchedArgs a) {
       uint32_t cnt[MB];
 #pragma unroll
       for (int q = 0; q < MB; ++q) cnt[q] = 0;
-      // bucket ids of this tile, then the next item's keys are requested
-      // (software pipelining across the claim) while the histogram is solved
+      // bucket ids of this tile, then the keys of the item after the next are
+      // requested while the histogram is solved: two items' loads in flight
+      // (one workgroup of these shapes fills a compute unit)
       uint32_t bk[NW];
 #pragma unroll
       for (int j = 0; j < NW; ++j) {
         const bool valid = wbase + (uint32_t)(j * kWave) + lane < tcount;
-        bk[j] = valid ? bf_pre(k[j]) : 0u;
+        bk[j] = valid ? bf_pre(kc[j]) : 0u;
       }
       // (only items of this claim: their records are the ones staged)
-      if (it + 1 < pre_end)
-        load_item(it + 1, std::false_type{});
-      else if (it + 1 < last)
-        load_item(it + 1, std::true_type{});  // the claim's first post-scan item
+      if (it + 2 < pre_end) load_keys(it + 2, kc);
       if constexpr (LANES) {
         // every element adds 1 to its lane's counter of its bucket: the 64
         // lanes of an instruction hit 64 distinct counters
@@ -314,16 +322,20 @@ __global__ void __launch_bounds__(WPB* kWave) batched_kernel(BatchedArgs a) {
       }
       __syncthreads();
       ++pub_count;
+    };
+    if (first < pre_end) load_keys(first, k);
+    if (first + 1 < pre_end) load_keys(first + 1, k2);
+    for (uint32_t it = first; it < pre_end; it += 2) {
+      pre_item(it, k);
+      if (it + 1 < pre_end) pre_item(it + 1, k2);
     }
     if (pub_count) publish();
 
     // ---- post-scan items of this claim; the wait (an acquire) is done
     // once per instance ----
-    // (the first post-scan item's keys and values were requested by the
-    // last pre-scan item of this claim, or are requested here)
     uint32_t seen = 0xFFFFFFFFu;
     const uint32_t post_first = first > P ? first : P;
-    if (post_first < last && first >= P) load_item(post_first, std::true_type{});
+    if (post_first < last) load_item(post_first, std::true_type{});
     for (uint32_t it = post_first; it < last; ++it) {
       const uint32_t tg = it - P;
       const uint4 r = s_info[it - first];
