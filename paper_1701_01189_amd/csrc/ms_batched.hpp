@@ -390,7 +390,11 @@ __global__ void __launch_bounds__(WPB* kWave) batched_kernel(BatchedArgs a) {
           tile_large<BITS, KV, WPB, NW, false, false>(bf_post, k, v, idv, false, tb, m, tcount, w,
                                                       lane, next);
       }
-      __syncthreads();
+      // No closing barrier (as between the tiles of a multisplit chunk): the
+      // next item's tile writes LDS only after its own first barrier; the
+      // running positions above 64 buckets (s_run), written before it, are
+      // read only before this tile's second barrier, which every wavefront
+      // has passed; s_flag is next written by a wavefront past both.
     }
   }
   if (Kind == kLearned && a.bp.mispredicts) {
