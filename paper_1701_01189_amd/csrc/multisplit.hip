@@ -421,13 +421,15 @@ ms_status run_multisplit(const uint32_t* ki, const uint32_t* vi, uint32_t* ko, u
     ids = (uint8_t*)ws + (total - align_up(n, kWsAlign));
   }
   const int post_kind = ids ? kPostKeptIds : fn->kind;
-  // Key-only block-level tiles up to 64 buckets: 4096 chunks.  A chunk's
-  // runs per bucket are then shorter and the write fronts of the resident
-  // workgroups closer together in each bucket's range; measured at 2^28
-  // keys, m = 32: post-scan 476 -> 457 us, whole call 359 -> 365 Gkeys/s;
-  // m = 8: 389 -> 399.  Key-value tiles and more buckets do not gain.
+  // Block-level tiles up to 64 buckets (key-value ones of at most 8
+  // wavefronts): 4096 chunks.  A chunk's runs per bucket are then shorter
+  // and the write fronts of the resident workgroups closer together in each
+  // bucket's range; measured at 2^28 keys, m = 32: post-scan 476 -> 457 us,
+  // whole call 359 -> 365 Gkeys/s; m = 8: 389 -> 399; 2^25 pairs, m = 32,
+  // 8 x 8: 233 -> 247 Gpairs/s.  16-wavefront key-value tiles (2^28 pairs,
+  // m = 32: 216 -> 211) and more buckets do not gain.
   const uint32_t min_chunks =
-      (!kv && m <= 64 && s.mode == ms::kBlock) ? kMaxChunks : kMinChunks;
+      (m <= 64 && s.mode == ms::kBlock && (!kv || s.wpb <= 8)) ? kMaxChunks : kMinChunks;
   Plan p = make_plan(n, m, s, resident_groups(post_kind, bits, kv, s), min_chunks);
   Workspace w = carve(ws, p);
   BucketParams bp = make_params(fn, m, opt ? opt->d_mispredicts : nullptr, div_mask);
